@@ -1,0 +1,2 @@
+from .circuits import *  # noqa: F401,F403
+from .circuits import Gate, pack  # noqa: F401
