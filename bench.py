@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused-gate state-vector path on one MI355X.
+
+Workload (one "step"): N=30 complex64 state initialised to |0...0>, the
+seeded random-brickwork circuit of depth 24 followed by a full 30-qubit QFT,
+greedily fused to blocks of at most 5 qubits (plan built once, outside the
+timed region, as in the paper's timing boundary), every fused block applied
+through the C-ABI, then 1000 shots sampled and decoded through the final
+layout map.
+
+Prints one JSON line.  ``value`` = fused gate-sweeps per second over whole
+steps (init + all sweeps + sampling).  ``roofline`` reports the dominant
+kernel (the k=5 MFMA sweep) from HIP events recorded around each of its
+launches inside the timed region, against the 8 TB/s HBM peak.
+``cpu_baseline`` times the CPU oracle on a bounded prefix of the same
+circuit on this host's cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_tile_mfma_k5_n30.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2608_16940_amd", "csrc", "sv_tile.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def pmc_traffic():
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3 counters, if current."""
+    try:
+        with open(PMC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha") != kernel_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(n, gates, n_blocks, seconds):
+    import oracle
+    psi = oracle.zero_state(n)
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(gates):
+        g = gates[done]
+        oracle.apply_gate(psi, g.matrix, g.targets)
+        done += 1
+        if time.perf_counter() - t0 >= seconds and done >= 3:
+            break
+    el = time.perf_counter() - t0
+    gate_rate = done / el
+    est_total = len(gates) / gate_rate
+    del psi
+    return {
+        "value": n_blocks / est_total,
+        "unit": "gate-sweeps/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": ("first %d of %d unfused gates of the same N=%d circuit, complex128, gate by gate "
+                   "(%.1f s); value = %d fused blocks / (%d gates / %.3f gates/s)"
+                   % (done, len(gates), n, el, n_blocks, len(gates), gate_rate)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--depth", type=int, default=24)
+    ap.add_argument("--kmax", type=int, default=5)
+    ap.add_argument("--shots", type=int, default=1000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path (requested --gpus %d, "
+              "WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2608_16940_amd as P
+    import workloads as W
+
+    n = args.n
+    gates = W.headline(n, args.depth, args.seed)
+    t0 = time.perf_counter()
+    plan = P.Plan.greedy(n, gates, args.kmax)
+    blocks = plan.blocks()
+    plan_s = time.perf_counter() - t0
+    nb = len(blocks)
+    kcount = {}
+    for b in blocks:
+        kcount[b["k"]] = kcount.get(b["k"], 0) + 1
+    kdom = max(kcount, key=lambda k: (kcount[k], k))
+    log("bench: n=%d gates=%d blocks=%d by_k=%s plan_s=%.2f" % (n, len(gates), nb, kcount, plan_s))
+
+    sv = P.StateVector(n, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    ndom = kcount[kdom]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(ndom * args.steps)]
+    dom_times = []
+
+    def step(timed_index):
+        sv.reset()
+        j = 0
+        for b in blocks:
+            if timed_index is not None and b["k"] == kdom:
+                e0, e1 = ev[timed_index * ndom + j]
+                e0.record(stream)
+                sv.apply(b["matrix"], b["targets"])
+                e1.record(stream)
+                j += 1
+            else:
+                sv.apply(b["matrix"], b["targets"])
+        return sv.sample(0x5EED, args.shots)
+
+    for w in range(args.warmup):
+        step(None)
+        torch.cuda.synchronize()
+        log("bench: warmup %d done" % w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(s)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for e0, e1 in ev:
+        dom_times.append(e0.elapsed_time(e1) / 1e3)
+    log("bench: timed %d steps in %.3f s" % (args.steps, el))
+
+    ms_per_step = el / args.steps * 1e3
+    value = nb * args.steps / el
+    sweep_bytes = 16.0 * (1 << n)
+    dom_avg = float(np.mean(dom_times))
+    achieved = sweep_bytes / dom_avg / 1e9
+    traffic = pmc_traffic()
+    st = sv.stats()
+    sv.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(n, gates, nb, args.cpu_seconds)
+
+    out = {
+        "metric": "fused gate-sweeps/s + HBM GB/s (% peak) at N=30 c64; learned vs greedy fusion",
+        "value": value,
+        "unit": "gate-sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "N=%d complex64 |0>: random brickwork depth %d (Haar SU(2) + CZ) then QFT%d; "
+                        "greedy fusion k<=%d; %d shots" % (n, args.depth, n, args.kmax, args.shots),
+            "n_qubits": n, "k_max": args.kmax, "gates": len(gates), "fused_blocks": nb,
+            "blocks_by_k": {str(k): v for k, v in sorted(kcount.items())}, "planner": "greedy",
+            "parallelism": "single GPU",
+        },
+        "effective_gbps_per_step": value * sweep_bytes / 1e9,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_tile_mfma<K=%d> fp32" % kdom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "launches": len(dom_times),
+            "avg_ms": dom_avg * 1e3,
+            "bytes_per_launch": sweep_bytes,
+        },
+        "cpu_baseline": cpu,
+        "stats_last_step": st,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,98 @@
+"""ctypes binding of libsv.so (argument marshalling only).
+
+Every function here forwards to the C-ABI declared in ``include/sv.h`` and
+``include/sv_plan.h``.  There is no fallback: if the library has not been
+built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsv.so")
+
+SV_OK = 0
+SV_ERR_ARG = -1
+SV_ERR_DEVICE = -2
+SV_ERR_UNSUPPORTED = -3
+SV_ERR_STATE = -4
+
+OPT_VARIANT = 1
+OPT_PRECISION = 2
+OPT_MFMA_MIN_K = 3
+OPT_LAZY_RELABEL = 4
+OPT_LOW_BITS = 5
+
+VARIANT = {"auto": 0, "valu": 1, "shuffle": 2, "mfma": 3, "generic": 4}
+PRECISION = {"fp32": 0, "bf16x3": 1}
+
+
+class SvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libsv error %d: %s" % (code, msg))
+        self.code = code
+
+
+class sv_stats(ctypes.Structure):
+    _fields_ = [("gate_sweeps", ctypes.c_int64), ("swap_half_sweeps", ctypes.c_int64),
+                ("relabels", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("by_variant", ctypes.c_int64 * 5)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_vp = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+SIGNATURES = [
+    ("sv_workspace_bytes", ctypes.c_size_t, [ctypes.c_int]),
+    ("sv_alloc", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp]),
+    ("sv_free", ctypes.c_int, [_vp]),
+    ("sv_reset", ctypes.c_int, [_vp]),
+    ("sv_apply_fused", ctypes.c_int, [_vp, _dp, _i32p, ctypes.c_int]),
+    ("sv_permute_layout", ctypes.c_int, [_vp, _i32p]),
+    ("sv_get_layout", ctypes.c_int, [_vp, _i32p]),
+    ("sv_probs", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    ("sv_norm", ctypes.c_int, [_vp, _dp]),
+    ("sv_sample", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int64, _u64p]),
+    ("sv_sample_probs", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, _u64p, _vp,
+                                       ctypes.c_size_t, _vp]),
+    ("sv_sync", ctypes.c_int, [_vp]),
+    ("sv_last_error", ctypes.c_char_p, []),
+    ("sv_set_option", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    ("sv_get_option", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    ("sv_get_stats", ctypes.c_int, [_vp, ctypes.POINTER(sv_stats)]),
+    ("sv_plan_greedy", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, _dp, ctypes.POINTER(ctypes.c_int8),
+                                      ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("sv_plan_num_blocks", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("sv_plan_block_info", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _i32p,
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    ("sv_plan_block_matrix", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    ("sv_run_plan", ctypes.c_int, [_vp, _vp]),
+    ("sv_plan_free", ctypes.c_int, [_vp]),
+]
+
+
+def lib():
+    """Load libsv.so (raises if it has not been built; there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsv.so not built at %s; run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> int:
+    if rc != SV_OK:
+        msg = lib().sv_last_error()
+        raise SvError(rc, msg.decode() if msg else "")
+    return rc

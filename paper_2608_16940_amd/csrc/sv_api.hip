@@ -1,0 +1,503 @@
+// C-ABI of libsv: handle management, layout map, kernel selection, operand
+// staging, probabilities, norm and sampling.  Host code only; kernels live in
+// sv_kernels.hip and sv_tile.hip.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+thread_local std::string g_err;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+size_t workspace_layout(int n, char *base, Workspace *ws) {
+  const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
+  const int64_t nc = (nb + 1023) / 1024;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t o_ring = take(size_t(kRingSlots) * kRingSlotBytes);
+  const size_t o_bs = take(size_t(nb) * 8);
+  const size_t o_cs = take(size_t(nc) * 8);
+  const size_t o_sh = take(size_t(kShotChunk) * 8);
+  const size_t o_pa = take(size_t(kNormPartials) * 8);
+  const size_t o_sc = take(64 * 8);
+  if (base && ws) {
+    ws->ring = base + o_ring;
+    ws->blocksum = reinterpret_cast<uint64_t *>(base + o_bs);
+    ws->chunksum = reinterpret_cast<uint64_t *>(base + o_cs);
+    ws->shots = reinterpret_cast<uint64_t *>(base + o_sh);
+    ws->partials = reinterpret_cast<double *>(base + o_pa);
+    ws->scalars = reinterpret_cast<uint64_t *>(base + o_sc);
+  }
+  return off;
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+struct sv_state {
+  int n = 0;
+  float2 *amps = nullptr;
+  char *ws_base = nullptr;
+  size_t ws_bytes = 0;
+  Workspace ws;
+  hipStream_t st = nullptr;
+  int32_t L[64];
+  int32_t Linv[64];
+  // options
+  int variant = SV_VARIANT_AUTO;
+  int prec = SV_PREC_FP32;
+  int mfma_min_k = 4;
+  int lazy = 0;
+  int low_bits = 5;
+  // operand staging ring
+  char *pinned = nullptr;
+  hipEvent_t ev[kRingSlots];
+  bool ev_live[kRingSlots];
+  int ring_next = 0;
+  sv_stats stats;
+};
+
+namespace {
+
+bool valid_n(int n) { return n >= SV_MIN_QUBITS && n <= SV_MAX_QUBITS; }
+
+void reset_layout(sv_state *s) {
+  for (int q = 0; q < s->n; ++q) s->L[q] = s->Linv[q] = q;
+}
+
+LayoutArg layout_arg(const sv_state *s) {
+  LayoutArg a;
+  std::memset(&a, 0, sizeof(a));
+  for (int q = 0; q < s->n; ++q) a.pos[q] = int8_t(s->L[q]);
+  return a;
+}
+
+// Stage `bytes` of host data into the next ring slot; returns the device pointer.
+int stage(sv_state *s, const void *host, size_t bytes, void **dev, int *slot_out) {
+  if (bytes > kRingSlotBytes) {
+    set_error("operand too large for a staging slot");
+    return SV_ERR_UNSUPPORTED;
+  }
+  const int slot = s->ring_next;
+  s->ring_next = (s->ring_next + 1) % kRingSlots;
+  if (s->ev_live[slot]) SV_HIP_CHECK(hipEventSynchronize(s->ev[slot]));
+  char *ph = s->pinned + size_t(slot) * kRingSlotBytes;
+  std::memcpy(ph, host, bytes);
+  char *dv = s->ws.ring + size_t(slot) * kRingSlotBytes;
+  SV_HIP_CHECK(hipMemcpyAsync(dv, ph, bytes, hipMemcpyHostToDevice, s->st));
+  *dev = dv;
+  *slot_out = slot;
+  return SV_OK;
+}
+
+int release_slot(sv_state *s, int slot) {
+  SV_HIP_CHECK(hipEventRecord(s->ev[slot], s->st));
+  s->ev_live[slot] = true;
+  return SV_OK;
+}
+
+void swap_physical(sv_state *s, int p, int q) {
+  const int a = s->Linv[p], b = s->Linv[q];
+  s->L[a] = q;
+  s->L[b] = p;
+  s->Linv[p] = b;
+  s->Linv[q] = a;
+}
+
+int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
+  const int n = s->n;
+  int v = s->variant;
+  const bool shuffle_ok = (k == 1 && A[0] <= 6);
+  const bool mfma_ok = (k >= 4 && k <= 7 && n >= k + mfma_tile_M(k));
+  const bool valu_ok = (k <= 4);
+  if (v == SV_VARIANT_AUTO) {
+    if (shuffle_ok)
+      v = SV_VARIANT_SHUFFLE;
+    else if (mfma_ok && k >= s->mfma_min_k)
+      v = SV_VARIANT_MFMA;
+    else if (valu_ok)
+      v = SV_VARIANT_VALU;
+    else
+      v = SV_VARIANT_GENERIC;
+  }
+  const int D = 1 << k;
+  hipError_t e = hipSuccess;
+  switch (v) {
+    case SV_VARIANT_SHUFFLE:
+    case SV_VARIANT_VALU: {
+      if ((v == SV_VARIANT_SHUFFLE && !shuffle_ok) || (v == SV_VARIANT_VALU && !valu_ok)) {
+        set_error("forced variant does not apply to this gate");
+        return SV_ERR_UNSUPPORTED;
+      }
+      float2 m[256];
+      for (int i = 0; i < D * D; ++i) m[i] = make_float2(float(matrix[2 * i]), float(matrix[2 * i + 1]));
+      e = (v == SV_VARIANT_SHUFFLE) ? launch_1q_shuffle(s->amps, n, A[0], m, s->st)
+                                    : launch_dense_valu(s->amps, n, k, A, m, s->st);
+      break;
+    }
+    case SV_VARIANT_MFMA: {
+      if (!mfma_ok) {
+        set_error("MFMA lowering needs 4 <= k <= 7 and a state of at least k + tile bits");
+        return SV_ERR_UNSUPPORTED;
+      }
+      TilePlan tp;
+      if (!make_gate_tile(n, k, A, &tp)) {
+        set_error("tile geometry failed");
+        return SV_ERR_UNSUPPORTED;
+      }
+      std::vector<char> buf(mfma_operand_bytes(k, s->prec));
+      pack_mfma_operand(k, s->prec, matrix, buf.data());
+      void *dev = nullptr;
+      int slot = 0;
+      int rc = stage(s, buf.data(), buf.size(), &dev, &slot);
+      if (rc) return rc;
+      e = launch_tile_mfma(tp, s->prec, s->amps, dev, s->st);
+      if (e == hipSuccess) {
+        rc = release_slot(s, slot);
+        if (rc) return rc;
+      }
+      break;
+    }
+    case SV_VARIANT_GENERIC: {
+      if (k > 8) {
+        set_error("generic lowering supports k <= 8");
+        return SV_ERR_UNSUPPORTED;
+      }
+      std::vector<float2> m(size_t(D) * D);
+      for (size_t i = 0; i < m.size(); ++i) m[i] = make_float2(float(matrix[2 * i]), float(matrix[2 * i + 1]));
+      void *dev = nullptr;
+      int slot = 0;
+      int rc = stage(s, m.data(), m.size() * sizeof(float2), &dev, &slot);
+      if (rc) return rc;
+      e = launch_dense_generic(s->amps, n, k, A, static_cast<const float2 *>(dev), s->st);
+      if (e == hipSuccess) {
+        rc = release_slot(s, slot);
+        if (rc) return rc;
+      }
+      break;
+    }
+    default:
+      set_error("unknown variant");
+      return SV_ERR_ARG;
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return SV_ERR_DEVICE;
+  }
+  s->stats.gate_sweeps += 1;
+  s->stats.launches += 1;
+  if (v >= 0 && v < 5) s->stats.by_variant[v] += 1;
+  return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+size_t sv_workspace_bytes(int n_qubits) {
+  if (!valid_n(n_qubits)) return 0;
+  return workspace_layout(n_qubits, nullptr, nullptr);
+}
+
+int sv_alloc(sv_state **out, int n, void *amps_dev, size_t amps_bytes, void *ws_dev, size_t ws_bytes,
+             void *stream) {
+  g_err.clear();
+  if (!out || !amps_dev || !ws_dev) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  *out = nullptr;
+  if (!valid_n(n)) {
+    set_error("n_qubits out of range [1, 35]");
+    return SV_ERR_ARG;
+  }
+  if (amps_bytes < (size_t(8) << n)) {
+    set_error("state buffer smaller than 8 * 2^N bytes");
+    return SV_ERR_ARG;
+  }
+  if (ws_bytes < sv_workspace_bytes(n)) {
+    set_error("workspace smaller than sv_workspace_bytes(N)");
+    return SV_ERR_ARG;
+  }
+  if ((reinterpret_cast<uintptr_t>(amps_dev) & 255) || (reinterpret_cast<uintptr_t>(ws_dev) & 255)) {
+    set_error("device buffers must be 256-byte aligned");
+    return SV_ERR_ARG;
+  }
+  sv_state *s = new sv_state();
+  s->n = n;
+  s->amps = static_cast<float2 *>(amps_dev);
+  s->ws_base = static_cast<char *>(ws_dev);
+  s->ws_bytes = ws_bytes;
+  workspace_layout(n, s->ws_base, &s->ws);
+  s->st = static_cast<hipStream_t>(stream);
+  std::memset(&s->stats, 0, sizeof(s->stats));
+  for (int i = 0; i < kRingSlots; ++i) s->ev_live[i] = false;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&s->pinned), size_t(kRingSlots) * kRingSlotBytes,
+                               hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_error(std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+    delete s;
+    return SV_ERR_DEVICE;
+  }
+  for (int i = 0; i < kRingSlots; ++i) {
+    e = hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      set_error(std::string("hipEventCreate failed: ") + hipGetErrorString(e));
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(s->ev[j]);
+      (void)hipHostFree(s->pinned);
+      delete s;
+      return SV_ERR_DEVICE;
+    }
+  }
+  reset_layout(s);
+  e = launch_init_zero(s->amps, n, s->st);
+  if (e != hipSuccess) {
+    set_error(std::string("init launch failed: ") + hipGetErrorString(e));
+    for (int j = 0; j < kRingSlots; ++j) (void)hipEventDestroy(s->ev[j]);
+    (void)hipHostFree(s->pinned);
+    delete s;
+    return SV_ERR_DEVICE;
+  }
+  *out = s;
+  return SV_OK;
+}
+
+int sv_free(sv_state *s) {
+  if (!s) return SV_OK;
+  (void)hipStreamSynchronize(s->st);
+  for (int i = 0; i < kRingSlots; ++i) (void)hipEventDestroy(s->ev[i]);
+  if (s->pinned) (void)hipHostFree(s->pinned);
+  delete s;
+  return SV_OK;
+}
+
+int sv_reset(sv_state *s) {
+  if (!s) {
+    set_error("null handle");
+    return SV_ERR_ARG;
+  }
+  reset_layout(s);
+  std::memset(&s->stats, 0, sizeof(s->stats));
+  SV_HIP_CHECK(launch_init_zero(s->amps, s->n, s->st));
+  return SV_OK;
+}
+
+int sv_apply_fused(sv_state *s, const double *matrix, const int32_t *targets, int k) {
+  if (!s || !matrix || !targets) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  if (k < 1 || k > s->n || k > SV_MAX_K) {
+    set_error("k out of range [1, min(N, SV_MAX_K)]");
+    return SV_ERR_ARG;
+  }
+  int32_t A[SV_MAX_K];
+  for (int j = 0; j < k; ++j) {
+    if (targets[j] < 0 || targets[j] >= s->n) {
+      set_error("target qubit out of range");
+      return SV_ERR_ARG;
+    }
+    for (int i = 0; i < j; ++i)
+      if (targets[i] == targets[j]) {
+        set_error("duplicate target qubit");
+        return SV_ERR_ARG;
+      }
+    A[j] = s->L[targets[j]];
+  }
+  return apply_physical(s, matrix, A, k);
+}
+
+int sv_permute_layout(sv_state *s, const int32_t *new_layout) {
+  if (!s || !new_layout) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  const int n = s->n;
+  bool seen[64] = {false};
+  for (int q = 0; q < n; ++q) {
+    const int p = new_layout[q];
+    if (p < 0 || p >= n || seen[p]) {
+      set_error("new layout is not a bijection");
+      return SV_ERR_ARG;
+    }
+    seen[p] = true;
+  }
+  // Selection order: fill physical positions 0..n-1 with their final qubits,
+  // one bit transposition at a time (Lemma 2: each swap updates L = tau o L).
+  for (int p = 0; p < n; ++p) {
+    int want = -1;
+    for (int q = 0; q < n; ++q)
+      if (new_layout[q] == p) want = q;
+    const int cur = s->L[want];
+    if (cur == p) continue;
+    SV_HIP_CHECK(launch_swap_bits(s->amps, n, p, cur, s->st));
+    swap_physical(s, p, cur);
+    s->stats.swap_half_sweeps += 1;
+    s->stats.launches += 1;
+  }
+  return SV_OK;
+}
+
+int sv_get_layout(const sv_state *s, int32_t *out) {
+  if (!s || !out) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  for (int q = 0; q < s->n; ++q) out[q] = s->L[q];
+  return SV_OK;
+}
+
+int sv_probs(sv_state *s, double *out_dev, int logical_order) {
+  if (!s || !out_dev) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  SV_HIP_CHECK(launch_probs(s->amps, s->n, out_dev, logical_order ? 1 : 0, layout_arg(s), s->st));
+  return SV_OK;
+}
+
+int sv_norm(sv_state *s, double *out_host) {
+  if (!s || !out_host) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  double *res = reinterpret_cast<double *>(s->ws.scalars);
+  SV_HIP_CHECK(launch_norm(s->amps, s->n, s->ws.partials, res, s->st));
+  SV_HIP_CHECK(hipMemcpyAsync(out_host, res, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  SV_HIP_CHECK(hipStreamSynchronize(s->st));
+  return SV_OK;
+}
+
+static int sample_impl(const float2 *psi, const double *probs, int n, const Workspace &ws, uint64_t seed,
+                       int64_t shots, uint64_t *out_host, const LayoutArg &L, hipStream_t st) {
+  SV_HIP_CHECK(launch_cdf_build(psi, probs, n, ws, st));
+  const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
+  uint64_t total = 0;
+  SV_HIP_CHECK(hipMemcpyAsync(&total, ws.blocksum + (nb - 1), 8, hipMemcpyDeviceToHost, st));
+  SV_HIP_CHECK(hipStreamSynchronize(st));
+  if (total == 0) {
+    set_error("zero total probability");
+    return SV_ERR_STATE;
+  }
+  for (int64_t s0 = 0; s0 < shots; s0 += kShotChunk) {
+    const int64_t cnt = std::min<int64_t>(kShotChunk, shots - s0);
+    SV_HIP_CHECK(launch_shots(psi, probs, n, ws, seed, s0, cnt, L, st));
+    SV_HIP_CHECK(hipMemcpyAsync(out_host + s0, ws.shots, size_t(cnt) * 8, hipMemcpyDeviceToHost, st));
+    SV_HIP_CHECK(hipStreamSynchronize(st));
+  }
+  return SV_OK;
+}
+
+int sv_sample(sv_state *s, uint64_t seed, int64_t shots, uint64_t *out_host) {
+  if (!s || (!out_host && shots > 0) || shots < 0) {
+    set_error("bad argument");
+    return SV_ERR_ARG;
+  }
+  if (shots == 0) return SV_OK;
+  return sample_impl(s->amps, nullptr, s->n, s->ws, seed, shots, out_host, layout_arg(s), s->st);
+}
+
+int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots, uint64_t *out_host,
+                    void *ws_dev, size_t ws_bytes, void *stream) {
+  if (!probs_dev || !ws_dev || (!out_host && shots > 0) || shots < 0 || !valid_n(n)) {
+    set_error("bad argument");
+    return SV_ERR_ARG;
+  }
+  if (ws_bytes < sv_workspace_bytes(n)) {
+    set_error("workspace smaller than sv_workspace_bytes(n)");
+    return SV_ERR_ARG;
+  }
+  if (shots == 0) return SV_OK;
+  Workspace ws;
+  workspace_layout(n, static_cast<char *>(ws_dev), &ws);
+  LayoutArg L;
+  std::memset(&L, 0, sizeof(L));
+  for (int q = 0; q < n; ++q) L.pos[q] = int8_t(q);
+  return sample_impl(nullptr, probs_dev, n, ws, seed, shots, out_host, L, static_cast<hipStream_t>(stream));
+}
+
+int sv_sync(sv_state *s) {
+  if (!s) {
+    set_error("null handle");
+    return SV_ERR_ARG;
+  }
+  SV_HIP_CHECK(hipStreamSynchronize(s->st));
+  return SV_OK;
+}
+
+int sv_set_option(sv_state *s, int key, int value) {
+  if (!s) {
+    set_error("null handle");
+    return SV_ERR_ARG;
+  }
+  switch (key) {
+    case SV_OPT_VARIANT:
+      if (value < SV_VARIANT_AUTO || value > SV_VARIANT_GENERIC) break;
+      s->variant = value;
+      return SV_OK;
+    case SV_OPT_PRECISION:
+      if (value != SV_PREC_FP32 && value != SV_PREC_BF16X3) break;
+      s->prec = value;
+      return SV_OK;
+    case SV_OPT_MFMA_MIN_K:
+      if (value < 4 || value > 8) break;
+      s->mfma_min_k = value;
+      return SV_OK;
+    case SV_OPT_LAZY_RELABEL:
+      s->lazy = value ? 1 : 0;
+      return SV_OK;
+    case SV_OPT_LOW_BITS:
+      if (value < 1 || value > 20) break;
+      s->low_bits = value;
+      return SV_OK;
+    default:
+      break;
+  }
+  set_error("bad option key or value");
+  return SV_ERR_ARG;
+}
+
+int sv_get_option(const sv_state *s, int key, int *value) {
+  if (!s || !value) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  switch (key) {
+    case SV_OPT_VARIANT: *value = s->variant; return SV_OK;
+    case SV_OPT_PRECISION: *value = s->prec; return SV_OK;
+    case SV_OPT_MFMA_MIN_K: *value = s->mfma_min_k; return SV_OK;
+    case SV_OPT_LAZY_RELABEL: *value = s->lazy; return SV_OK;
+    case SV_OPT_LOW_BITS: *value = s->low_bits; return SV_OK;
+    default: break;
+  }
+  set_error("bad option key");
+  return SV_ERR_ARG;
+}
+
+int sv_get_stats(const sv_state *s, sv_stats *out) {
+  if (!s || !out) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  *out = s->stats;
+  return SV_OK;
+}
+
+}  // extern "C"

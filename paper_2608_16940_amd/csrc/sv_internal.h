@@ -1,0 +1,110 @@
+// Internal declarations shared by the libsv translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "sv.h"
+
+namespace sv {
+
+// ------------------------------------------------------------------ workspace
+// Matrix ring: per-apply operands travel host -> pinned staging slot ->
+// device slot with one async copy; a slot is reused only after the event
+// recorded after its copy has completed.
+constexpr int kRingSlots = 16;
+constexpr size_t kRingSlotBytes = 512 * 1024;  // k <= 8 complex64 matrix, or k <= 7 packed MFMA operand
+constexpr int64_t kShotChunk = int64_t(1) << 20;
+constexpr int kNormPartials = 2048;
+constexpr int kCdfBlockBits = 10;  // hierarchical-CDF block of 2^10 entries (Section IV-E)
+
+struct Workspace {
+  char *ring = nullptr;          // kRingSlots * kRingSlotBytes
+  uint64_t *blocksum = nullptr;  // nb entries: inclusive prefix of block totals after the scan
+  uint64_t *chunksum = nullptr;  // ceil(nb / 1024) chunk totals
+  uint64_t *shots = nullptr;     // kShotChunk decoded outcomes
+  double *partials = nullptr;    // kNormPartials FP64 partial sums
+  uint64_t *scalars = nullptr;   // 64 small results
+};
+
+// Bytes needed for an n-qubit workspace; if base != nullptr also fills *ws.
+size_t workspace_layout(int n, char *base, Workspace *ws);
+
+// ------------------------------------------------------------------ layout argument
+struct LayoutArg {
+  int8_t pos[64];  // pos[q] = physical bit of logical qubit q
+};
+
+// ------------------------------------------------------------------ error reporting
+void set_error(const std::string &msg);
+#define SV_HIP_CHECK(expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      ::sv::set_error(std::string(#expr) + " failed: " + hipGetErrorString(e_));        \
+      return SV_ERR_DEVICE;                                                             \
+    }                                                                                   \
+  } while (0)
+
+// ------------------------------------------------------------------ kernels: launchers
+// All launchers enqueue on `st` and return the launch status.
+
+// |0...0>
+hipError_t launch_init_zero(float2 *psi, int n, hipStream_t st);
+
+// k <= 4, per-thread group gather/FMA/scatter.  m: complex64 row-major 2^k x 2^k (host).
+hipError_t launch_dense_valu(float2 *psi, int n, int k, const int32_t *phys_targets, const float2 *m,
+                             hipStream_t st);
+
+// k = 1 on physical bit b <= 6 with wavefront shuffles.  m: 2x2 complex64 (host).
+hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStream_t st);
+
+// any k <= 8; m_dev: device complex64 row-major matrix.
+hipError_t launch_dense_generic(float2 *psi, int n, int k, const int32_t *phys_targets, const float2 *m_dev,
+                                hipStream_t st);
+
+// Exchange physical bits p and q (a bit transposition; half the amplitudes move).
+hipError_t launch_swap_bits(float2 *psi, int n, int p, int q, hipStream_t st);
+
+hipError_t launch_probs(const float2 *psi, int n, double *out, int logical, const LayoutArg &L, hipStream_t st);
+hipError_t launch_norm(const float2 *psi, int n, double *partials, double *result, hipStream_t st);
+
+// Sampler.  src_state != nullptr: probabilities from the state; else from probs.
+hipError_t launch_cdf_build(const float2 *src_state, const double *src_probs, int n, const Workspace &ws,
+                            hipStream_t st);
+hipError_t launch_shots(const float2 *src_state, const double *src_probs, int n, const Workspace &ws,
+                        uint64_t seed, int64_t shot0, int64_t count, const LayoutArg &L, hipStream_t st);
+
+// ------------------------------------------------------------------ LDS-tiled kernels
+// A tile is the set of 2^s amplitudes that share every physical bit outside
+// the tile mask S.  Bits of the tile-order index v (s bits, ascending physical
+// position) are scattered into the local (LDS) index: on load bit b of v goes
+// to local bit loc_in[b]; on store local bit loc_out[b] supplies bit b of the
+// output tile-order index (loc_out == loc_in means no relabel).
+struct TilePlan {
+  int n = 0, s = 0, K = 0, M = 0;
+  uint64_t smask = 0;
+  int sbit[32] = {0};
+  int loc_in[32] = {0};
+  int loc_out[32] = {0};
+};
+
+// Real-embedded, lane-major MFMA operand for gate matrix G (FP64 host, 2^K x 2^K).
+// prec = SV_PREC_FP32: float; SV_PREC_BF16X3: uint16 hi then lo planes.
+size_t mfma_operand_bytes(int K, int prec);
+void pack_mfma_operand(int K, int prec, const double *G, void *out);
+
+// Tile geometry for a dense gate on physical targets A (gate order).  Returns false
+// if the state is too small for the MFMA tiling.
+bool make_gate_tile(int n, int K, const int32_t *A, TilePlan *tp);
+int mfma_tile_M(int K);
+
+hipError_t launch_tile_mfma(const TilePlan &tp, int prec, float2 *psi, const void *operand_dev, hipStream_t st);
+
+// Pure bit permutation within a tile: tp.loc_out describes where each tile bit goes.
+hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st);
+
+}  // namespace sv

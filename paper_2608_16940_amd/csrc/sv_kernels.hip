@@ -1,0 +1,527 @@
+// Streaming kernels of the state-vector path for gfx950 (wave64):
+//   - |0...0> initialisation,
+//   - per-thread dense gate apply for k <= 4 (vector ALU),
+//   - single-qubit apply with cross-lane exchange for low physical bits,
+//   - a generic one-group-per-workgroup apply for any k <= 8,
+//   - physical bit transposition (the on-demand layout swap),
+//   - FP64 probabilities and norm,
+//   - the two-level integer CDF sampler.
+// Every index is 64-bit: the state reaches 2^35 amplitudes.
+#include "sv_internal.h"
+
+namespace sv {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int64_t insert_zero_bit(int64_t x, int p) {
+  const int64_t low = x & ((int64_t(1) << p) - 1);
+  return ((x >> p) << (p + 1)) | low;
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+
+inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 20) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return unsigned(g);
+}
+
+// ------------------------------------------------------------------ init
+__global__ __launch_bounds__(kThreads) void k_init_zero(float4 *psi4, int64_t n4, float2 *psi) {
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n4; i += stride)
+    psi4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (blockIdx.x == 0 && threadIdx.x == 0) psi[0] = make_float2(1.f, 0.f);
+}
+
+__global__ void k_init_small(float2 *psi, int64_t dim) {
+  for (int64_t i = threadIdx.x; i < dim; i += blockDim.x) psi[i] = make_float2(i == 0 ? 1.f : 0.f, 0.f);
+}
+
+// ------------------------------------------------------------------ dense, vector ALU
+template <int K>
+struct ValuArgs {
+  float2 m[1 << (2 * K)];   // row-major complex64
+  int64_t off[1 << K];      // in-group offset of amplitude c: sum_j bit_j(c) << A_j
+  int sorted[K];            // target positions ascending
+};
+
+// One thread owns one group of 2^K amplitudes.  Consecutive threads take
+// consecutive values of the non-target bits, lowest first, so a wave's loads
+// are contiguous whenever the low physical bits are not targets.
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_dense_valu(float2 *__restrict__ psi, int64_t ngroups,
+                                                         ValuArgs<K> a) {
+  constexpr int D = 1 << K;
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < ngroups; g += stride) {
+    int64_t base = g;
+#pragma unroll
+    for (int j = 0; j < K; ++j) base = insert_zero_bit(base, a.sorted[j]);
+    float2 in[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) in[c] = psi[base + a.off[c]];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc = cfma(a.m[r * D + c], in[c], acc);
+      psi[base + a.off[r]] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ single qubit, wave exchange
+// Each lane holds two consecutive amplitudes (one 16-byte load).  For target
+// bit 0 the pair is inside the lane; for bit b in 1..6 the partner pair sits
+// in lane (lane ^ 2^(b-1)) of the same wave and arrives by a cross-lane
+// shuffle, so every load and store of the wave is one contiguous 1 KiB run.
+__global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ psi4, int64_t nchunks, int b,
+                                                         float2 m00, float2 m01, float2 m10, float2 m11) {
+  const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  const bool active = t < nchunks;
+  float4 v = active ? psi4[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 a0 = make_float2(v.x, v.y), a1 = make_float2(v.z, v.w);
+  float2 o0, o1;
+  if (b == 0) {
+    o0 = cfma(m01, a1, cmul(m00, a0));
+    o1 = cfma(m11, a1, cmul(m10, a0));
+  } else {
+    const int mask = 1 << (b - 1);
+    float4 p;
+    p.x = __shfl_xor(v.x, mask);
+    p.y = __shfl_xor(v.y, mask);
+    p.z = __shfl_xor(v.z, mask);
+    p.w = __shfl_xor(v.w, mask);
+    const float2 p0 = make_float2(p.x, p.y), p1 = make_float2(p.z, p.w);
+    if ((t >> (b - 1)) & 1) {  // this lane's amplitudes have bit b = 1; partners have bit b = 0
+      o0 = cfma(m11, a0, cmul(m10, p0));
+      o1 = cfma(m11, a1, cmul(m10, p1));
+    } else {
+      o0 = cfma(m01, p0, cmul(m00, a0));
+      o1 = cfma(m01, p1, cmul(m00, a1));
+    }
+  }
+  if (active) psi4[t] = make_float4(o0.x, o0.y, o1.x, o1.y);
+}
+
+// ------------------------------------------------------------------ generic, any k <= 8
+struct GenericArgs {
+  int k;
+  int sorted[8];
+  int tgt[8];
+};
+
+__global__ __launch_bounds__(kThreads) void k_dense_generic(float2 *__restrict__ psi, int64_t ngroups,
+                                                            const float2 *__restrict__ m, GenericArgs a) {
+  __shared__ float2 buf[256];
+  const int D = 1 << a.k;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    int64_t base = g;
+    for (int j = 0; j < a.k; ++j) base = insert_zero_bit(base, a.sorted[j]);
+    for (int c = threadIdx.x; c < D; c += kThreads) {
+      int64_t off = 0;
+      for (int j = 0; j < a.k; ++j) off |= int64_t((c >> j) & 1) << a.tgt[j];
+      buf[c] = psi[base + off];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < D; r += kThreads) {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int c = 0; c < D; ++c) acc = cfma(m[int64_t(r) * D + c], buf[c], acc);
+      int64_t off = 0;
+      for (int j = 0; j < a.k; ++j) off |= int64_t((r >> j) & 1) << a.tgt[j];
+      psi[base + off] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ physical bit transposition
+// For every index with bit p = 0 and bit q = 0 (p < q), exchange the
+// amplitudes at x | 2^q and x | 2^p.  Consecutive threads take consecutive
+// values of the remaining bits.
+__global__ __launch_bounds__(kThreads) void k_swap_bits(float2 *__restrict__ psi, int64_t m, int p, int q) {
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x; t < m; t += stride) {
+    const int64_t x = insert_zero_bit(insert_zero_bit(t, p), q);
+    const int64_t ia = x | (int64_t(1) << q);
+    const int64_t ib = x | (int64_t(1) << p);
+    const float2 va = psi[ia];
+    const float2 vb = psi[ib];
+    psi[ia] = vb;
+    psi[ib] = va;
+  }
+}
+
+// ------------------------------------------------------------------ probabilities and norm
+__device__ __forceinline__ double prob_of(float2 a) {
+  // Both products are exact in FP64 (24-bit significands), so the one rounding
+  // of the sum is the only one, with or without contraction into an FMA.
+  return double(a.x) * double(a.x) + double(a.y) * double(a.y);
+}
+
+__device__ __forceinline__ int64_t logical_to_physical(int64_t x, int n, const LayoutArg &L) {
+  int64_t y = 0;
+  for (int q = 0; q < n; ++q) y |= ((x >> q) & 1) << L.pos[q];
+  return y;
+}
+
+__device__ __forceinline__ uint64_t physical_to_logical(uint64_t y, int n, const LayoutArg &L) {
+  uint64_t x = 0;
+  for (int q = 0; q < n; ++q) x |= ((y >> L.pos[q]) & 1ull) << q;
+  return x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_probs(const float2 *__restrict__ psi, int64_t dim, int n,
+                                                    double *__restrict__ out, int logical, LayoutArg L) {
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < dim; x += stride) {
+    const int64_t y = logical ? logical_to_physical(x, n, L) : x;
+    out[x] = prob_of(psi[y]);
+  }
+}
+
+// Deterministic two-pass FP64 norm: fixed per-thread ranges, fixed tree.
+__global__ __launch_bounds__(kThreads) void k_norm_partial(const float2 *__restrict__ psi, int64_t dim,
+                                                           double *__restrict__ partials) {
+  __shared__ double red[kThreads];
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  double s = 0.0;
+  for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < dim; x += stride) s += prob_of(psi[x]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_norm_final(const double *__restrict__ partials, int np,
+                                                         double *__restrict__ result) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *result = red[0];
+}
+
+// ------------------------------------------------------------------ sampler
+// Fixed-point probability: q = floor(p * 2^62), exact (power-of-two scaling,
+// truncating conversion).  Integer sums are exact and order-independent, so
+// the block totals do not depend on the reduction tree.
+__device__ __forceinline__ uint64_t fixed_q(double p) { return (uint64_t)(p * 4611686018427387904.0); }
+
+__device__ __forceinline__ uint64_t q_at(const float2 *psi, const double *probs, int64_t i) {
+  return fixed_q(psi ? prob_of(psi[i]) : probs[i]);
+}
+
+// One workgroup per 2^10-entry block: exact block total.
+__global__ __launch_bounds__(kThreads) void k_block_totals(const float2 *__restrict__ psi,
+                                                           const double *__restrict__ probs, int64_t dim,
+                                                           uint64_t *__restrict__ blocksum) {
+  __shared__ uint64_t red[kThreads];
+  const int64_t b0 = int64_t(blockIdx.x) << kCdfBlockBits;
+  uint64_t s = 0;
+  for (int i = threadIdx.x; i < (1 << kCdfBlockBits); i += kThreads) {
+    const int64_t x = b0 + i;
+    if (x < dim) s += q_at(psi, probs, x);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0];
+}
+
+// Inclusive scan of 1024-element chunks in place (256 threads x 4), chunk total out.
+__global__ __launch_bounds__(kThreads) void k_scan_chunks(uint64_t *__restrict__ v, int64_t nb,
+                                                          uint64_t *__restrict__ chunk_total) {
+  __shared__ uint64_t sh[kThreads];
+  const int64_t c0 = int64_t(blockIdx.x) * 1024;
+  uint64_t loc[4];
+  uint64_t run = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t idx = c0 + threadIdx.x * 4 + i;
+    run += (idx < nb) ? v[idx] : 0ull;
+    loc[i] = run;
+  }
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread totals
+  for (int off = 1; off < kThreads; off <<= 1) {
+    uint64_t add = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0ull;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint64_t excl = (threadIdx.x > 0) ? sh[threadIdx.x - 1] : 0ull;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t idx = c0 + threadIdx.x * 4 + i;
+    if (idx < nb) v[idx] = loc[i] + excl;
+  }
+  if (threadIdx.x == kThreads - 1) chunk_total[blockIdx.x] = sh[kThreads - 1];
+}
+
+// One workgroup: exclusive scan of the chunk totals in place (sequential per thread slice).
+__global__ __launch_bounds__(kThreads) void k_scan_totals(uint64_t *__restrict__ t, int64_t nc) {
+  __shared__ uint64_t sh[kThreads];
+  const int64_t per = (nc + kThreads - 1) / kThreads;
+  const int64_t lo = threadIdx.x * per;
+  const int64_t hi = lo + per < nc ? lo + per : nc;
+  uint64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += t[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    uint64_t add = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0ull;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint64_t run = (threadIdx.x > 0) ? sh[threadIdx.x - 1] : 0ull;
+  for (int64_t i = lo; i < hi; ++i) {
+    const uint64_t v = t[i];
+    t[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_add(uint64_t *__restrict__ v, int64_t nb,
+                                                       const uint64_t *__restrict__ chunk_excl) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < nb) v[i] += chunk_excl[i >> 10];
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): per round two 32x32 -> 64-bit
+// products of counter words 0 and 2 with the multipliers; the high halves are
+// mixed into words 1 and 3 with the round key, which grows by the Weyl
+// increments after each round.
+__device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint64_t ctr) {
+  uint32_t x0 = uint32_t(ctr), x1 = uint32_t(ctr >> 32), x2 = 0u, x3 = 0u;
+  uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo_a = 0xD2511F53u * x0, hi_a = __umulhi(0xD2511F53u, x0);
+    const uint32_t lo_b = 0xCD9E8D57u * x2, hi_b = __umulhi(0xCD9E8D57u, x2);
+    const uint32_t y0 = hi_b ^ x1 ^ k0;
+    const uint32_t y2 = hi_a ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo_b;
+    x2 = y2;
+    x3 = lo_a;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return uint64_t(x0) | (uint64_t(x1) << 32);
+}
+
+// One wave per shot.  The block is found by binary search over the inclusive
+// block prefix; inside the block each lane owns 16 consecutive entries, a wave
+// prefix over lane totals finds the owning lane, which then scans its entries.
+__global__ __launch_bounds__(kThreads) void k_shots(const float2 *__restrict__ psi,
+                                                    const double *__restrict__ probs, int n, int64_t dim,
+                                                    const uint64_t *__restrict__ cprefix, int64_t nb,
+                                                    uint64_t seed, int64_t shot0, int64_t count, LayoutArg L,
+                                                    uint64_t *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t sidx = (int64_t(blockIdx.x) * kThreads + threadIdx.x) >> 6;
+  if (sidx >= count) return;  // whole waves exit together
+  const uint64_t total = cprefix[nb - 1];
+  const uint64_t r = philox_draw(seed, uint64_t(shot0 + sidx));
+  const uint64_t t = __umul64hi(r, total);  // floor(r * T / 2^64) < T
+  // smallest block b with cprefix[b] > t
+  int64_t lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (cprefix[mid] > t)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int64_t b = lo;
+  const uint64_t tin = t - (b > 0 ? cprefix[b - 1] : 0ull);
+  const int64_t base = b << kCdfBlockBits;
+  uint64_t q[16];
+  uint64_t mine = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t x = base + lane * 16 + i;
+    q[i] = (x < dim) ? q_at(psi, probs, x) : 0ull;
+    mine += q[i];
+  }
+  // inclusive wave prefix of lane totals
+  uint64_t incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t up = __shfl_up(incl, off);
+    if (lane >= off) incl += up;
+  }
+  const uint64_t excl = incl - mine;
+  const unsigned long long owner_mask = __ballot(incl > tin);
+  const int owner = __ffsll(owner_mask) - 1;  // the block total exceeds tin, so some lane owns it
+  if (lane == owner) {
+    uint64_t run = excl;
+    int pick = 15;
+    for (int i = 0; i < 16; ++i) {
+      run += q[i];
+      if (run > tin) {
+        pick = i;
+        break;
+      }
+    }
+    const uint64_t y = uint64_t(base + lane * 16 + pick);
+    out[sidx] = physical_to_logical(y, n, L);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_init_zero(float2 *psi, int n, hipStream_t st) {
+  const int64_t dim = int64_t(1) << n;
+  if (dim < 4) {
+    hipLaunchKernelGGL(k_init_small, dim3(1), dim3(64), 0, st, psi, dim);
+  } else {
+    const int64_t n4 = dim / 2;
+    hipLaunchKernelGGL(k_init_zero, dim3(grid_for(n4, kThreads, 65536)), dim3(kThreads), 0, st,
+                       reinterpret_cast<float4 *>(psi), n4, psi);
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t dense_valu_k(float2 *psi, int n, const int32_t *A, const float2 *m, hipStream_t st) {
+  ValuArgs<K> a;
+  for (int i = 0; i < (1 << (2 * K)); ++i) a.m[i] = m[i];
+  for (int c = 0; c < (1 << K); ++c) {
+    int64_t o = 0;
+    for (int j = 0; j < K; ++j)
+      if ((c >> j) & 1) o |= int64_t(1) << A[j];
+    a.off[c] = o;
+  }
+  int s[K];
+  for (int j = 0; j < K; ++j) s[j] = A[j];
+  for (int i = 1; i < K; ++i)
+    for (int j = i; j > 0 && s[j - 1] > s[j]; --j) {
+      int t = s[j];
+      s[j] = s[j - 1];
+      s[j - 1] = t;
+    }
+  for (int j = 0; j < K; ++j) a.sorted[j] = s[j];
+  const int64_t ngroups = int64_t(1) << (n - K);
+  hipLaunchKernelGGL(k_dense_valu<K>, dim3(grid_for(ngroups, kThreads, 1 << 16)), dim3(kThreads), 0, st, psi,
+                     ngroups, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_valu(float2 *psi, int n, int k, const int32_t *A, const float2 *m, hipStream_t st) {
+  switch (k) {
+    case 1: return dense_valu_k<1>(psi, n, A, m, st);
+    case 2: return dense_valu_k<2>(psi, n, A, m, st);
+    case 3: return dense_valu_k<3>(psi, n, A, m, st);
+    case 4: return dense_valu_k<4>(psi, n, A, m, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStream_t st) {
+  if (n < 1 || b < 0 || b > 6 || b >= n) return hipErrorInvalidValue;
+  const int64_t nchunks = int64_t(1) << (n - 1);
+  const int64_t blocks = (nchunks + kThreads - 1) / kThreads;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_1q_shuffle, dim3(unsigned(blocks)), dim3(kThreads), 0, st,
+                     reinterpret_cast<float4 *>(psi), nchunks, b, m[0], m[1], m[2], m[3]);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_generic(float2 *psi, int n, int k, const int32_t *A, const float2 *m_dev, hipStream_t st) {
+  if (k < 1 || k > 8 || k > n) return hipErrorInvalidValue;
+  GenericArgs a;
+  a.k = k;
+  int s[8];
+  for (int j = 0; j < k; ++j) s[j] = a.tgt[j] = A[j];
+  for (int i = 1; i < k; ++i)
+    for (int j = i; j > 0 && s[j - 1] > s[j]; --j) {
+      int t = s[j];
+      s[j] = s[j - 1];
+      s[j - 1] = t;
+    }
+  for (int j = 0; j < k; ++j) a.sorted[j] = s[j];
+  for (int j = k; j < 8; ++j) a.sorted[j] = a.tgt[j] = 0;
+  const int64_t ngroups = int64_t(1) << (n - k);
+  hipLaunchKernelGGL(k_dense_generic, dim3(grid_for(ngroups, 1, 1 << 16)), dim3(kThreads), 0, st, psi, ngroups,
+                     m_dev, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_swap_bits(float2 *psi, int n, int p, int q, hipStream_t st) {
+  if (p == q || p < 0 || q < 0 || p >= n || q >= n) return hipErrorInvalidValue;
+  if (p > q) {
+    int t = p;
+    p = q;
+    q = t;
+  }
+  const int64_t m = int64_t(1) << (n - 2);
+  hipLaunchKernelGGL(k_swap_bits, dim3(grid_for(m, kThreads, 1 << 16)), dim3(kThreads), 0, st, psi, m, p, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_probs(const float2 *psi, int n, double *out, int logical, const LayoutArg &L, hipStream_t st) {
+  const int64_t dim = int64_t(1) << n;
+  hipLaunchKernelGGL(k_probs, dim3(grid_for(dim, kThreads, 1 << 16)), dim3(kThreads), 0, st, psi, dim, n, out,
+                     logical, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm(const float2 *psi, int n, double *partials, double *result, hipStream_t st) {
+  const int64_t dim = int64_t(1) << n;
+  const unsigned g = grid_for(dim, kThreads * 16, kNormPartials);
+  hipLaunchKernelGGL(k_norm_partial, dim3(g), dim3(kThreads), 0, st, psi, dim, partials);
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kThreads), 0, st, partials, int(g), result);
+  return hipGetLastError();
+}
+
+hipError_t launch_cdf_build(const float2 *psi, const double *probs, int n, const Workspace &ws, hipStream_t st) {
+  const int64_t dim = int64_t(1) << n;
+  const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
+  hipLaunchKernelGGL(k_block_totals, dim3(unsigned(nb)), dim3(kThreads), 0, st, psi, probs, dim, ws.blocksum);
+  const int64_t nc = (nb + 1023) / 1024;
+  hipLaunchKernelGGL(k_scan_chunks, dim3(unsigned(nc)), dim3(kThreads), 0, st, ws.blocksum, nb, ws.chunksum);
+  if (nc > 1) {
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kThreads), 0, st, ws.chunksum, nc);
+    hipLaunchKernelGGL(k_scan_add, dim3(unsigned((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                       ws.blocksum, nb, ws.chunksum);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_shots(const float2 *psi, const double *probs, int n, const Workspace &ws, uint64_t seed,
+                        int64_t shot0, int64_t count, const LayoutArg &L, hipStream_t st) {
+  const int64_t dim = int64_t(1) << n;
+  const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
+  const int64_t threads = count * 64;
+  hipLaunchKernelGGL(k_shots, dim3(unsigned((threads + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, psi,
+                     probs, n, dim, ws.blocksum, nb, seed, shot0, count, L, ws.shots);
+  return hipGetLastError();
+}
+
+}  // namespace sv

@@ -1,0 +1,213 @@
+// Fusion planning on the host: greedy block formation and FP64 block products.
+#include "sv_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace sv {
+void set_error(const std::string &msg);
+}
+
+struct SvBlock {
+  int k = 0;
+  int ngates = 0;
+  bool diag = true;
+  std::vector<int32_t> tuple;    // ordered logical targets (ascending)
+  std::vector<double> matrix;    // complex128 interleaved, 2^k x 2^k
+};
+
+struct sv_plan {
+  int n = 0;
+  std::vector<SvBlock> blocks;
+};
+
+namespace {
+
+struct GateView {
+  int k;
+  const int32_t *t;
+  const double *m;
+  bool diag;
+};
+
+// M <- E(g) M, where E(g) is gate g embedded into the block's k-qubit space:
+// each column of M is a k-qubit vector and g acts on the local positions of
+// its targets inside the block tuple.
+void left_multiply(std::vector<double> &M, int k, const GateView &g, const std::vector<int32_t> &tuple) {
+  const int D = 1 << k;
+  const int d = 1 << g.k;
+  int loc[8];
+  for (int j = 0; j < g.k; ++j)
+    for (int b = 0; b < k; ++b)
+      if (tuple[b] == g.t[j]) loc[j] = b;
+  int gmask = 0;
+  for (int j = 0; j < g.k; ++j) gmask |= 1 << loc[j];
+  std::vector<double> in(2 * d), out(2 * d);
+  for (int col = 0; col < D; ++col) {
+    for (int rest = 0; rest < D; ++rest) {
+      if (rest & gmask) continue;  // enumerate the non-target local bits once
+      for (int c = 0; c < d; ++c) {
+        int idx = rest;
+        for (int j = 0; j < g.k; ++j)
+          if ((c >> j) & 1) idx |= 1 << loc[j];
+        in[2 * c] = M[2 * (size_t(idx) * D + col)];
+        in[2 * c + 1] = M[2 * (size_t(idx) * D + col) + 1];
+      }
+      for (int r = 0; r < d; ++r) {
+        double re = 0, im = 0;
+        for (int c = 0; c < d; ++c) {
+          const double gr = g.m[2 * (r * d + c)], gi = g.m[2 * (r * d + c) + 1];
+          re += gr * in[2 * c] - gi * in[2 * c + 1];
+          im += gr * in[2 * c + 1] + gi * in[2 * c];
+        }
+        out[2 * r] = re;
+        out[2 * r + 1] = im;
+      }
+      for (int r = 0; r < d; ++r) {
+        int idx = rest;
+        for (int j = 0; j < g.k; ++j)
+          if ((r >> j) & 1) idx |= 1 << loc[j];
+        M[2 * (size_t(idx) * D + col)] = out[2 * r];
+        M[2 * (size_t(idx) * D + col) + 1] = out[2 * r + 1];
+      }
+    }
+  }
+}
+
+SvBlock make_block(const std::vector<GateView> &gates) {
+  SvBlock b;
+  for (const auto &g : gates)
+    for (int j = 0; j < g.k; ++j)
+      if (std::find(b.tuple.begin(), b.tuple.end(), g.t[j]) == b.tuple.end()) b.tuple.push_back(g.t[j]);
+  std::sort(b.tuple.begin(), b.tuple.end());
+  b.k = int(b.tuple.size());
+  b.ngates = int(gates.size());
+  const int D = 1 << b.k;
+  b.matrix.assign(size_t(2) * D * D, 0.0);
+  for (int i = 0; i < D; ++i) b.matrix[2 * (size_t(i) * D + i)] = 1.0;
+  for (const auto &g : gates) {
+    b.diag = b.diag && g.diag;
+    left_multiply(b.matrix, b.k, g, b.tuple);
+  }
+  return b;
+}
+
+bool parse_gates(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
+                 const int8_t *diag, std::vector<GateView> *out) {
+  size_t toff = 0, moff = 0;
+  for (int i = 0; i < ngates; ++i) {
+    const int k = ks[i];
+    if (k < 1 || k > 8 || k > n) return false;
+    const int32_t *t = targets + toff;
+    for (int j = 0; j < k; ++j) {
+      if (t[j] < 0 || t[j] >= n) return false;
+      for (int a = 0; a < j; ++a)
+        if (t[a] == t[j]) return false;
+    }
+    out->push_back(GateView{k, t, mats + moff, diag ? diag[i] != 0 : false});
+    toff += size_t(k);
+    moff += size_t(2) << (2 * k);
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sv_plan_greedy(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
+                   const int8_t *diag, int k_max, sv_plan **out) {
+  if (!out || (ngates > 0 && (!ks || !targets || !mats)) || ngates < 0 || k_max < 1 || k_max > 8 ||
+      n < SV_MIN_QUBITS || n > SV_MAX_QUBITS) {
+    sv::set_error("bad planner argument");
+    return SV_ERR_ARG;
+  }
+  std::vector<GateView> gates;
+  if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
+    sv::set_error("bad gate in list");
+    return SV_ERR_ARG;
+  }
+  sv_plan *p = new sv_plan();
+  p->n = n;
+  std::vector<GateView> cur;
+  std::vector<int32_t> cur_set;
+  auto flush = [&]() {
+    if (!cur.empty()) p->blocks.push_back(make_block(cur));
+    cur.clear();
+    cur_set.clear();
+  };
+  for (const auto &g : gates) {
+    if (g.k > k_max) {
+      flush();
+      cur.push_back(g);
+      flush();
+      continue;
+    }
+    std::vector<int32_t> u = cur_set;
+    for (int j = 0; j < g.k; ++j)
+      if (std::find(u.begin(), u.end(), g.t[j]) == u.end()) u.push_back(g.t[j]);
+    if (int(u.size()) > k_max) {
+      flush();
+      u.assign(g.t, g.t + g.k);
+    }
+    cur.push_back(g);
+    cur_set = u;
+  }
+  flush();
+  *out = p;
+  return SV_OK;
+}
+
+int sv_plan_num_blocks(const sv_plan *p, int *out) {
+  if (!p || !out) {
+    sv::set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  *out = int(p->blocks.size());
+  return SV_OK;
+}
+
+int sv_plan_block_info(const sv_plan *p, int i, int *k, int32_t *targets, int *ngates, int *diag) {
+  if (!p || i < 0 || i >= int(p->blocks.size())) {
+    sv::set_error("bad block index");
+    return SV_ERR_ARG;
+  }
+  const SvBlock &b = p->blocks[size_t(i)];
+  if (k) *k = b.k;
+  if (targets)
+    for (int j = 0; j < b.k; ++j) targets[j] = b.tuple[size_t(j)];
+  if (ngates) *ngates = b.ngates;
+  if (diag) *diag = b.diag ? 1 : 0;
+  return SV_OK;
+}
+
+int sv_plan_block_matrix(const sv_plan *p, int i, double *out) {
+  if (!p || !out || i < 0 || i >= int(p->blocks.size())) {
+    sv::set_error("bad block index");
+    return SV_ERR_ARG;
+  }
+  const SvBlock &b = p->blocks[size_t(i)];
+  std::memcpy(out, b.matrix.data(), b.matrix.size() * sizeof(double));
+  return SV_OK;
+}
+
+int sv_run_plan(sv_state *s, const sv_plan *p) {
+  if (!s || !p) {
+    sv::set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  for (const SvBlock &b : p->blocks) {
+    const int rc = sv_apply_fused(s, b.matrix.data(), b.tuple.data(), b.k);
+    if (rc) return rc;
+  }
+  return SV_OK;
+}
+
+int sv_plan_free(sv_plan *p) {
+  delete p;
+  return SV_OK;
+}
+
+}  // extern "C"
