@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, run one plain device copy of the state's size "
+                         "(reference dispatch for scaling HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -159,6 +162,11 @@ def main():
     achieved = sweep_bytes / dom_avg / 1e9
     traffic = pmc_traffic()
     st = sv.stats()
+    if args.copy_probe:
+        dst = torch.empty_like(sv.amps)
+        dst.copy_(sv.amps)
+        torch.cuda.synchronize()
+        del dst
     sv.close()
 
     cpu = None

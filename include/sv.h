@@ -159,6 +159,12 @@ const char *sv_last_error(void);
 /* Physical bits below this count as "low" for the relabel policy (default 5). */
 #define SV_OPT_LOW_BITS 5
 
+/* Where the waves of a k <= 5 MFMA sweep keep the embedded gate operand:
+ * in their own registers, or once per workgroup in LDS (default). */
+#define SV_OPT_MFMA_OPERAND 6
+#define SV_MFMA_OPERAND_REGS 0
+#define SV_MFMA_OPERAND_LDS 1
+
 int sv_set_option(sv_state *s, int key, int value);
 int sv_get_option(const sv_state *s, int key, int *value);
 

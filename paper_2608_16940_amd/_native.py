@@ -23,6 +23,8 @@ OPT_PRECISION = 2
 OPT_MFMA_MIN_K = 3
 OPT_LAZY_RELABEL = 4
 OPT_LOW_BITS = 5
+OPT_MFMA_OPERAND = 6
+MFMA_OPERAND = {"regs": 0, "lds": 1}
 
 VARIANT = {"auto": 0, "valu": 1, "shuffle": 2, "mfma": 3, "generic": 4}
 PRECISION = {"fp32": 0, "bf16x3": 1}

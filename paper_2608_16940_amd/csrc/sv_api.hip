@@ -64,6 +64,7 @@ struct sv_state {
   int mfma_min_k = 4;
   int lazy = 0;
   int low_bits = 5;
+  int opsrc = SV_MFMA_OPERAND_LDS;
   // operand staging ring
   char *pinned = nullptr;
   hipEvent_t ev[kRingSlots];
@@ -166,7 +167,7 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
       int slot = 0;
       int rc = stage(s, buf.data(), buf.size(), &dev, &slot);
       if (rc) return rc;
-      e = launch_tile_mfma(tp, s->prec, s->amps, dev, s->st);
+      e = launch_tile_mfma(tp, s->prec, s->opsrc, s->amps, dev, s->st);
       if (e == hipSuccess) {
         rc = release_slot(s, slot);
         if (rc) return rc;
@@ -467,6 +468,10 @@ int sv_set_option(sv_state *s, int key, int value) {
       if (value < 1 || value > 20) break;
       s->low_bits = value;
       return SV_OK;
+    case SV_OPT_MFMA_OPERAND:
+      if (value != SV_MFMA_OPERAND_REGS && value != SV_MFMA_OPERAND_LDS) break;
+      s->opsrc = value;
+      return SV_OK;
     default:
       break;
   }
@@ -485,6 +490,7 @@ int sv_get_option(const sv_state *s, int key, int *value) {
     case SV_OPT_MFMA_MIN_K: *value = s->mfma_min_k; return SV_OK;
     case SV_OPT_LAZY_RELABEL: *value = s->lazy; return SV_OK;
     case SV_OPT_LOW_BITS: *value = s->low_bits; return SV_OK;
+    case SV_OPT_MFMA_OPERAND: *value = s->opsrc; return SV_OK;
     default: break;
   }
   set_error("bad option key");

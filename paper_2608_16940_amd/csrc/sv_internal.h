@@ -102,7 +102,9 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out);
 bool make_gate_tile(int n, int K, const int32_t *A, TilePlan *tp);
 int mfma_tile_M(int K);
 
-hipError_t launch_tile_mfma(const TilePlan &tp, int prec, float2 *psi, const void *operand_dev, hipStream_t st);
+// opsrc: SV_MFMA_OPERAND_* (where k <= 5 waves keep the embedded operand).
+hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi, const void *operand_dev,
+                            hipStream_t st);
 
 // Pure bit permutation within a tile: tp.loc_out describes where each tile bit goes.
 hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st);

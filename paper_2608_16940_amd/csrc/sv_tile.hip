@@ -2,28 +2,35 @@
 //
 // Dense fused gate on MFMA.  A fused k-qubit gate is a dense contraction
 // (Eq. cost-formal: Theta(2^{N+k}) complex multiply-adds): every group of
-// 2^k amplitudes that share the non-target bits is multiplied by G.  Here a
-// workgroup owns a tile of 2^(K+M) amplitudes -- the K target bits plus the M
-// lowest non-target physical bits -- so every global access is a contiguous
+// 2^k amplitudes that share the non-target bits is multiplied by G.  A
+// workgroup owns one tile of 2^(K+M) amplitudes -- the K target bits plus the
+// M lowest non-target physical bits -- so every global access is a contiguous
 // run of at least 2^M amplitudes whatever the target positions are.  The tile
 // is staged in LDS in "local" order (target bits lowest, in gate order, then
 // the non-target bits), which makes each group contiguous; each wave then
-// multiplies 32 groups at a time with the real embedding of G,
-//   [Re out; Im out] = [[Re G, -Im G], [Im G, Re G]] [Re in; Im in],
-// as a 2^(K+1) x 2^(K+1) by 2^(K+1) x 32 real GEMM on
-// v_mfma_f32_32x32x2f32 (FP32) or v_mfma_f32_32x32x8bf16_1k (BF16x3 split).
+// multiplies 32 groups at a time on the matrix cores:
 //
-// Operand layout.  The K (reduction) ordering is free, so lane l of a wave
-// holds group (l mod 32) and the contiguous half h = l / 32 of its 2^(K+1)
-// reals; MFMA step kk consumes the lane's kk-th real.  The output rows of the
-// embedded matrix are permuted on the host so that accumulator register r of
-// M-tile mt of lane l is output real (2^K h + 16 mt + r): a lane's results are
-// the same contiguous half of the same group, written back in place.
+//   * FP32, k = 4: the real embedding
+//       [Re y; Im y] = [[Re G, -Im G], [Im G, Re G]] [Re x; Im x]
+//     as a 2^(K+1) x 2^(K+1) by 2^(K+1) x 32 real GEMM (v_mfma_f32_32x32x2f32);
+//   * FP32, k >= 5: the three-multiplication complex product
+//       T1 = Gr Xr, T2 = Gi Xi, T3 = (Gr + Gi)(Xr + Xi),
+//       Re y = T1 - T2, Im y = T3 - T1 - T2,
+//     three 2^K x 2^K real GEMMs, 25% fewer MFMA cycles than the embedding;
+//   * BF16x3 (any k): the embedding with each operand split x = hi + lo in
+//     bf16 and hi*hi + hi*lo + lo*hi accumulated in FP32
+//     (v_mfma_f32_32x32x8bf16_1k); G is split once on the host from FP64.
+//
+// Operand layout.  The reduction ordering is free, so lane l of a wave holds
+// group (l mod 32) and the contiguous half h = l / 32 of its inputs; MFMA step
+// kk consumes the lane's kk-th input value.  The output rows are permuted on
+// the host so that accumulator register r of output tile mt of lane l is the
+// same contiguous half of the same group: results go back in place.
 //
 // The store side can read the tile with a different bit map (loc_out), which
 // relabels bits inside the tile for free (the lazy relabel L' = alpha o L of
-// Algorithm 2, restricted to the tile's bits).  With no gate the same kernel is
-// an in-place bit permutation in one sweep.
+// Algorithm 2, restricted to the tile's bits).  Without a gate the same
+// structure is an in-place bit permutation in one sweep (k_tile_permute).
 #include <cstring>
 
 #include "sv_internal.h"
@@ -32,7 +39,19 @@ namespace sv {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// Amplitudes are touched exactly once per sweep: stream them with
+// non-temporal loads and stores so they do not displace cached operands.
+__device__ __forceinline__ float4 ld_stream(const float2 *p) {
+  const floatx4 v = __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_stream(float2 *p, float2 a, float2 b) {
+  const floatx4 v = {a.x, a.y, b.x, b.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<floatx4 *>(p));
+}
 
 struct TileArgs {
   float2 *psi;
@@ -70,18 +89,39 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(unsigned(h) << 16); }
 
-template <int K, int M, int PREC>
+// Where a wave finds the gate operand: its own registers (loaded once per
+// workgroup), the workgroup's LDS (loaded once, read per MFMA), or global
+// memory through the caches (read per MFMA; only for the widest gates).
+enum OpSrc { OP_REG = 0, OP_LDS = 1, OP_GLOBAL = 2 };
+// Arithmetic scheme.
+enum Alg { ALG_EMBED_F32 = 0, ALG_GAUSS_F32 = 1, ALG_EMBED_BF16X3 = 2 };
+
+template <int K, int PREC>
+struct Scheme {
+  static constexpr int alg = (PREC == SV_PREC_BF16X3) ? ALG_EMBED_BF16X3 : (K >= 5 ? ALG_GAUSS_F32 : ALG_EMBED_F32);
+  // operand bytes (see pack_mfma_operand)
+  static constexpr int bytes = (alg == ALG_GAUSS_F32) ? 3 * (1 << (2 * K + 2)) : (1 << (2 * K + 4));
+};
+
+template <int K, int M, int PREC, int OPS>
 __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
   constexpr int WAVES = 1 << (M - 5);
   constexpr int NT = 64 * WAVES;
   constexpr int S = K + M;
   constexpr int TILE = 1 << S;
   constexpr int CHUNKS = 1 << (K - 2);  // 16-byte chunks per thread per tile
-  constexpr int HALF = 1 << K;          // reals per lane half
-  constexpr int MT = (2 << K) / 32;     // 32-row output tiles
-  constexpr int AH = HALF / 2;          // amplitudes per lane half
-  constexpr bool RESIDENT = (K <= 5);   // embedded operand held in registers
+  constexpr int AH = 1 << (K - 1);      // amplitudes per lane half
+  constexpr int ALG = Scheme<K, PREC>::alg;
+  constexpr int NOPF = Scheme<K, PREC>::bytes / 4;  // operand size in floats
+  // embedding: 2^(K+1) real outputs in 32-row tiles, 2^K reals per lane half
+  constexpr int EMT = (2 << K) / 32;
+  constexpr int HALF = 1 << K;
+  constexpr int KQ = HALF / 4;
+  // Gauss: 2^K complex outputs in 32-row tiles, AH amplitudes per lane half
+  constexpr int GMT = (1 << K) / 32;
+  constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * GMT : EMT;
   __shared__ float2 lds[TILE];
+  __shared__ float opl_s[OPS == OP_LDS ? NOPF : 1];
 
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -100,29 +140,31 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
   const int bin = 1 << a.lb_in, bout = 1 << a.lb_out;
 
   // ---- operand
-  constexpr int NRES = RESIDENT ? (PREC == SV_PREC_FP32 ? MT * HALF : MT * (HALF / 4) * 2) : 1;
-  float ra[NRES];
-  shortx4 rh[RESIDENT && PREC == SV_PREC_BF16X3 ? MT * (HALF / 4) : 1];
-  shortx4 rl[RESIDENT && PREC == SV_PREC_BF16X3 ? MT * (HALF / 4) : 1];
   const float *opf = reinterpret_cast<const float *>(a.op);
-  const shortx4 *oph = reinterpret_cast<const shortx4 *>(a.op);
-  const shortx4 *opl = oph + MT * (HALF / 4) * 64;
-  if constexpr (RESIDENT) {
-    if constexpr (PREC == SV_PREC_FP32) {
-#pragma unroll
-      for (int i = 0; i < MT * HALF; ++i) ra[i] = opf[i * 64 + lane];
-    } else {
-#pragma unroll
-      for (int i = 0; i < MT * (HALF / 4); ++i) {
-        rh[i] = oph[i * 64 + lane];
-        rl[i] = opl[i * 64 + lane];
-      }
-    }
-  }
+  constexpr int NREG = (OPS == OP_REG) ? NOPF / 64 : 1;
+  float ra[NREG];
   (void)ra;
+  if constexpr (OPS == OP_REG) {
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) ra[i] = opf[i * 64 + lane];
+  } else if constexpr (OPS == OP_LDS) {
+    const float4 *src = reinterpret_cast<const float4 *>(a.op);
+    float4 *dst = reinterpret_cast<float4 *>(opl_s);
+    for (int i = t; i < NOPF / 4; i += NT) dst[i] = src[i];
+    // visible after the first barrier below
+  }
+  const float *opsrc = (OPS == OP_LDS) ? static_cast<const float *>(opl_s) : opf;
+  // operand float i of this lane (i indexes the lane-major packing)
+  auto opv = [&](int i) -> float {
+    if constexpr (OPS == OP_REG)
+      return ra[i];
+    else
+      return opsrc[i * 64 + lane];
+  };
 
   const int g = 32 * wave + (lane & 31);
   const int h = lane >> 5;
+  const int gbase = g << K;
 
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     int64_t base = tile;
@@ -130,86 +172,111 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
     for (int b = 0; b < S; ++b) base = insert_zero_bit(base, a.sbit[b]);
 
     // ---- global -> LDS (each chunk: two consecutive amplitudes, 16 B)
+    float4 v[CHUNKS];
+#pragma unroll
+    for (int i = 0; i < CHUNKS; ++i) v[i] = ld_stream(a.psi + base + goff_t + a.goff_i[i]);
 #pragma unroll
     for (int i = 0; i < CHUNKS; ++i) {
-      const float4 v = *reinterpret_cast<const float4 *>(a.psi + base + goff_t + a.goff_i[i]);
       const int l0 = lam_t | a.lam_i[i];
-      lds[swz<K>(l0)] = make_float2(v.x, v.y);
-      lds[swz<K>(l0 | bin)] = make_float2(v.z, v.w);
+      lds[swz<K>(l0)] = make_float2(v[i].x, v[i].y);
+      lds[swz<K>(l0 | bin)] = make_float2(v[i].z, v[i].w);
     }
     __syncthreads();
 
-    // ---- 32 groups per wave: gather this lane's half group
-    float bx[HALF];
+    // Each wave reads and then overwrites only its own 32 groups; LDS
+    // operations of one wave complete in order, so no barrier is needed
+    // between its reads and its writes.
+    floatx16 acc[NACC];
 #pragma unroll
-    for (int e = 0; e < AH; ++e) {
-      const float2 x = lds[swz<K>((g << K) | (h * AH + e))];
-      bx[2 * e] = x.x;
-      bx[2 * e + 1] = x.y;
-    }
-    floatx16 acc[MT];
+    for (int m = 0; m < NACC; ++m)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[mt][r] = 0.f;
+      for (int r = 0; r < 16; ++r) acc[m][r] = 0.f;
 
-    if constexpr (PREC == SV_PREC_FP32) {
+    if constexpr (ALG == ALG_GAUSS_F32) {
+      // step kk uses amplitude (AH h + kk) of this lane's group
+      constexpr int UNR = (K <= 5) ? AH : 8;
+#pragma unroll UNR
+      for (int kk = 0; kk < AH; ++kk) {
+        const float2 x = lds[swz<K>(gbase | (h * AH + kk))];
+        const float xs = x.x + x.y;
 #pragma unroll
-      for (int kk = 0; kk < HALF; ++kk) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          float av;
-          if constexpr (RESIDENT)
-            av = ra[mt * HALF + kk];
-          else
-            av = opf[(mt * HALF + kk) * 64 + lane];
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bx[kk], acc[mt], 0, 0, 0);
+        for (int mt = 0; mt < GMT; ++mt) {
+          const int i0 = (0 * GMT + mt) * AH + kk;
+          const int i1 = (1 * GMT + mt) * AH + kk;
+          const int i2 = (2 * GMT + mt) * AH + kk;
+          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(i0), x.x, acc[mt], 0, 0, 0);
+          acc[GMT + mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(i1), x.y, acc[GMT + mt], 0, 0, 0);
+          acc[2 * GMT + mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(i2), xs, acc[2 * GMT + mt], 0, 0, 0);
         }
       }
-    } else {
 #pragma unroll
-      for (int kk = 0; kk < HALF / 4; ++kk) {
+      for (int mt = 0; mt < GMT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float t1 = acc[mt][r], t2 = acc[GMT + mt][r], t3 = acc[2 * GMT + mt][r];
+          lds[swz<K>(gbase | (h * AH + 16 * mt + r))] = make_float2(t1 - t2, t3 - t1 - t2);
+        }
+    } else if constexpr (ALG == ALG_EMBED_F32) {
+      // step kk uses real (HALF h + kk) of this lane's group
+#pragma unroll
+      for (int kk = 0; kk < HALF; ++kk) {
+        const float2 x = lds[swz<K>(gbase | (h * AH + (kk >> 1)))];
+        const float xv = (kk & 1) ? x.y : x.x;
+#pragma unroll
+        for (int mt = 0; mt < EMT; ++mt)
+          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(mt * HALF + kk), xv, acc[mt], 0, 0, 0);
+      }
+#pragma unroll
+      for (int mt = 0; mt < EMT; ++mt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[mt][2 * e], acc[mt][2 * e + 1]);
+    } else {
+      const shortx4 *oph = reinterpret_cast<const shortx4 *>(opsrc);
+      constexpr int UNR = (K <= 5) ? KQ : 4;
+#pragma unroll UNR
+      for (int kk = 0; kk < KQ; ++kk) {
+        // four reals = two amplitudes (AH h + 2 kk, +1)
+        const float2 x0 = lds[swz<K>(gbase | (h * AH + 2 * kk))];
+        const float2 x1 = lds[swz<K>(gbase | (h * AH + 2 * kk + 1))];
+        const float xr[4] = {x0.x, x0.y, x1.x, x1.y};
         shortx4 bh, bl;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float x = bx[4 * kk + e];
-          const unsigned short hi = bf16_rne(x);
-          const unsigned short lo = bf16_rne(x - bf16_to_f(hi));
+          const unsigned short hi = bf16_rne(xr[e]);
+          const unsigned short lo = bf16_rne(xr[e] - bf16_to_f(hi));
           bh[e] = short(hi);
           bl[e] = short(lo);
         }
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
+        for (int mt = 0; mt < EMT; ++mt) {
           shortx4 ah, al;
-          if constexpr (RESIDENT) {
-            ah = rh[mt * (HALF / 4) + kk];
-            al = rl[mt * (HALF / 4) + kk];
+          if constexpr (OPS == OP_REG) {
+            const int ih = 2 * (mt * KQ + kk), il = 2 * (EMT * KQ + mt * KQ + kk);
+            ah = __builtin_bit_cast(shortx4, make_float2(ra[ih], ra[ih + 1]));
+            al = __builtin_bit_cast(shortx4, make_float2(ra[il], ra[il + 1]));
           } else {
-            ah = oph[(mt * (HALF / 4) + kk) * 64 + lane];
-            al = opl[(mt * (HALF / 4) + kk) * 64 + lane];
+            ah = oph[(mt * KQ + kk) * 64 + lane];
+            al = oph[(EMT * KQ + mt * KQ + kk) * 64 + lane];
           }
           acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[mt], 0, 0, 0);
           acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[mt], 0, 0, 0);
           acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[mt], 0, 0, 0);
         }
       }
+#pragma unroll
+      for (int mt = 0; mt < EMT; ++mt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[mt][2 * e], acc[mt][2 * e + 1]);
     }
-
-    // ---- results back to the same LDS slots (this wave owns these groups)
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        lds[swz<K>((g << K) | (h * AH + 8 * mt + e))] = make_float2(acc[mt][2 * e], acc[mt][2 * e + 1]);
     __syncthreads();
 
     // ---- LDS -> global
 #pragma unroll
     for (int i = 0; i < CHUNKS; ++i) {
       const int l0 = lamo_t | a.lamo_i[i];
-      const float2 x0 = lds[swz<K>(l0)];
-      const float2 x1 = lds[swz<K>(l0 | bout)];
-      *reinterpret_cast<float4 *>(a.psi + base + goff_t + a.goff_i[i]) = make_float4(x0.x, x0.y, x1.x, x1.y);
+      st_stream(a.psi + base + goff_t + a.goff_i[i], lds[swz<K>(l0)], lds[swz<K>(l0 | bout)]);
     }
     __syncthreads();
   }
@@ -236,36 +303,23 @@ __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
     int64_t base = tile;
 #pragma unroll
     for (int b = 0; b < S; ++b) base = insert_zero_bit(base, a.sbit[b]);
+    float4 v[CHUNKS];
+#pragma unroll
+    for (int i = 0; i < CHUNKS; ++i) v[i] = ld_stream(a.psi + base + goff_t + a.goff_i[i]);
 #pragma unroll
     for (int i = 0; i < CHUNKS; ++i) {
-      const float4 v = *reinterpret_cast<const float4 *>(a.psi + base + goff_t + a.goff_i[i]);
       const int l0 = 2 * (i * NT + t);  // identity on load
-      lds[l0] = make_float2(v.x, v.y);
-      lds[l0 + 1] = make_float2(v.z, v.w);
+      lds[l0] = make_float2(v[i].x, v[i].y);
+      lds[l0 + 1] = make_float2(v[i].z, v[i].w);
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < CHUNKS; ++i) {
       const int l0 = lamo_t | a.lamo_i[i];
-      const float2 x0 = lds[l0];
-      const float2 x1 = lds[l0 | bout];
-      *reinterpret_cast<float4 *>(a.psi + base + goff_t + a.goff_i[i]) = make_float4(x0.x, x0.y, x1.x, x1.y);
+      st_stream(a.psi + base + goff_t + a.goff_i[i], lds[l0], lds[l0 | bout]);
     }
     __syncthreads();
   }
-}
-
-int g_cu_count = 0;
-int cu_count() {
-  if (g_cu_count == 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) ==
-                                                 hipSuccess && v > 0)
-      g_cu_count = v;
-    else
-      g_cu_count = 256;
-  }
-  return g_cu_count;
 }
 
 int64_t pdep_host(uint64_t v, const int *sbit, int s) {
@@ -302,17 +356,29 @@ void fill_args(const TilePlan &tp, int nt, int chunks, float2 *psi, const void *
   }
 }
 
-float embedded(const double *G, int K, int orow, int icol) {
-  const int D = 1 << K;
-  const int r = orow >> 1, po = orow & 1, c = icol >> 1, pi = icol & 1;
-  const double gr = G[2 * (r * D + c)], gi = G[2 * (r * D + c) + 1];
-  double v = (po == pi) ? gr : (po == 0 ? -gi : gi);
-  return float(v);
+// One tile per workgroup: the dispatcher then walks memory in order, which
+// measured faster than persistent workgroups striding over the state.
+unsigned grid_of(int64_t ntiles) { return unsigned(ntiles > 0x7fffffff ? 0x7fffffff : ntiles); }
+
+template <int K, int M, int PREC, int OPS>
+hipError_t tile_mfma_k(const TilePlan &tp, float2 *psi, const void *op, hipStream_t st) {
+  constexpr int NT = 64 << (M - 5);
+  constexpr int CHUNKS = 1 << (K - 2);
+  TileArgs a;
+  fill_args(tp, NT, CHUNKS, psi, op, &a);
+  hipLaunchKernelGGL((k_tile_mfma<K, M, PREC, OPS>), dim3(grid_of(a.ntiles)), dim3(NT), 0, st, a);
+  return hipGetLastError();
 }
-double embedded64(const double *G, int K, int orow, int icol) {
+
+double re_of(const double *G, int D, int r, int c) { return G[2 * (r * D + c)]; }
+double im_of(const double *G, int D, int r, int c) { return G[2 * (r * D + c) + 1]; }
+
+// entry (orow, icol) of the real embedding [[Re G, -Im G], [Im G, Re G]] with
+// interleaved (re, im) rows and columns
+double embedded(const double *G, int K, int orow, int icol) {
   const int D = 1 << K;
   const int r = orow >> 1, po = orow & 1, c = icol >> 1, pi = icol & 1;
-  const double gr = G[2 * (r * D + c)], gi = G[2 * (r * D + c) + 1];
+  const double gr = re_of(G, D, r, c), gi = im_of(G, D, r, c);
   return (po == pi) ? gr : (po == 0 ? -gi : gi);
 }
 
@@ -329,18 +395,9 @@ float host_bf16_to_f(uint16_t h) {
   return f;
 }
 
-template <int K, int M, int PREC>
-hipError_t tile_mfma_k(const TilePlan &tp, float2 *psi, const void *op, hipStream_t st) {
-  constexpr int NT = 64 << (M - 5);
-  constexpr int CHUNKS = 1 << (K - 2);
-  TileArgs a;
-  fill_args(tp, NT, CHUNKS, psi, op, &a);
-  const int per_cu = (NT >= 256) ? 3 : 8;
-  int64_t grid = int64_t(cu_count()) * per_cu;
-  if (grid > a.ntiles) grid = a.ntiles;
-  hipLaunchKernelGGL((k_tile_mfma<K, M, PREC>), dim3(unsigned(grid)), dim3(NT), 0, st, a);
-  return hipGetLastError();
-}
+// Output-row order that makes accumulator register r of lane half h hold row
+// (half * h + 16 mt + r): row i of 32x32 output tile mt is stored there.
+int out_row(int half, int mt, int i) { return half * ((i >> 2) & 1) + 16 * mt + 4 * (i >> 3) + (i & 3); }
 
 }  // namespace
 
@@ -387,50 +444,66 @@ bool make_gate_tile(int n, int K, const int32_t *A, TilePlan *tp) {
 }
 
 size_t mfma_operand_bytes(int K, int prec) {
-  (void)prec;
+  if (prec == SV_PREC_FP32 && K >= 5) return size_t(3) << (2 * K + 2);
   return size_t(1) << (2 * K + 4);
 }
 
 void pack_mfma_operand(int K, int prec, const double *G, void *out) {
-  const int HALF = 1 << K;
-  const int MT = (2 << K) / 32;
-  if (prec == SV_PREC_FP32) {
+  const int D = 1 << K;
+  const int HALF = 1 << K, AH = 1 << (K - 1);
+  const int EMT = (2 << K) / 32;
+  if (prec == SV_PREC_FP32 && K >= 5) {
+    // three planes Gr, Gi, Gr + Gi; plane x, tile mt, step kk, lane l holds
+    // X[out_row(AH, mt, l % 32)][AH * (l / 32) + kk]
+    const int GMT = D / 32;
     float *o = static_cast<float *>(out);
-    for (int mt = 0; mt < MT; ++mt)
+    for (int x = 0; x < 3; ++x)
+      for (int mt = 0; mt < GMT; ++mt)
+        for (int kk = 0; kk < AH; ++kk)
+          for (int l = 0; l < 64; ++l) {
+            const int r = out_row(AH, mt, l & 31), c = AH * (l >> 5) + kk;
+            const double gr = re_of(G, D, r, c), gi = im_of(G, D, r, c);
+            const double val = (x == 0) ? gr : (x == 1 ? gi : gr + gi);
+            o[((x * GMT + mt) * AH + kk) * 64 + l] = float(val);
+          }
+  } else if (prec == SV_PREC_FP32) {
+    // embedding; tile mt, step kk, lane l holds R[out_row(HALF, mt, l % 32)][HALF * (l / 32) + kk]
+    float *o = static_cast<float *>(out);
+    for (int mt = 0; mt < EMT; ++mt)
       for (int kk = 0; kk < HALF; ++kk)
-        for (int l = 0; l < 64; ++l) {
-          const int i = l & 31, kp = l >> 5;
-          const int orow = HALF * ((i >> 2) & 1) + 16 * mt + 4 * (i >> 3) + (i & 3);
-          const int icol = HALF * kp + kk;
-          o[(mt * HALF + kk) * 64 + l] = embedded(G, K, orow, icol);
-        }
+        for (int l = 0; l < 64; ++l)
+          o[(mt * HALF + kk) * 64 + l] = float(embedded(G, K, out_row(HALF, mt, l & 31), HALF * (l >> 5) + kk));
   } else {
+    // embedding split in bf16 hi and lo planes; four consecutive reductions per step
+    const int KQ = HALF / 4;
     uint16_t *hi = static_cast<uint16_t *>(out);
-    uint16_t *lo = hi + size_t(MT) * (HALF / 4) * 64 * 4;
-    for (int mt = 0; mt < MT; ++mt)
-      for (int kk = 0; kk < HALF / 4; ++kk)
+    uint16_t *lo = hi + size_t(EMT) * KQ * 64 * 4;
+    for (int mt = 0; mt < EMT; ++mt)
+      for (int kk = 0; kk < KQ; ++kk)
         for (int l = 0; l < 64; ++l)
           for (int e = 0; e < 4; ++e) {
-            const int i = l & 31, kp = l >> 5;
-            const int orow = HALF * ((i >> 2) & 1) + 16 * mt + 4 * (i >> 3) + (i & 3);
-            const int icol = HALF * kp + 4 * kk + e;
-            const double v = embedded64(G, K, orow, icol);
-            const uint16_t h = host_bf16_rne(float(v));
-            const uint16_t l16 = host_bf16_rne(float(v - double(host_bf16_to_f(h))));
-            const size_t idx = ((size_t(mt) * (HALF / 4) + kk) * 64 + l) * 4 + e;
-            hi[idx] = h;
+            const double v = embedded(G, K, out_row(HALF, mt, l & 31), HALF * (l >> 5) + 4 * kk + e);
+            const uint16_t h16 = host_bf16_rne(float(v));
+            const uint16_t l16 = host_bf16_rne(float(v - double(host_bf16_to_f(h16))));
+            const size_t idx = ((size_t(mt) * KQ + kk) * 64 + l) * 4 + e;
+            hi[idx] = h16;
             lo[idx] = l16;
           }
   }
 }
 
-hipError_t launch_tile_mfma(const TilePlan &tp, int prec, float2 *psi, const void *op, hipStream_t st) {
+hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi, const void *op, hipStream_t st) {
   const bool bf = (prec == SV_PREC_BF16X3);
+  const bool regs = (opsrc == SV_MFMA_OPERAND_REGS);
   switch (tp.K) {
-    case 4: return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32>(tp, psi, op, st);
-    case 5: return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32>(tp, psi, op, st);
-    case 6: return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32>(tp, psi, op, st);
-    case 7: return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32>(tp, psi, op, st);
+    case 4:
+      if (regs) return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
+      return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+    case 5:
+      if (regs) return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
+      return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+    case 6: return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+    case 7: return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -442,9 +515,7 @@ hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st) 
   constexpr int CHUNKS = (1 << (S - 1)) / NT;
   TileArgs a;
   fill_args(tp, NT, CHUNKS, psi, nullptr, &a);
-  int64_t grid = int64_t(cu_count()) * 4;
-  if (grid > a.ntiles) grid = a.ntiles;
-  hipLaunchKernelGGL((k_tile_permute<S>), dim3(unsigned(grid)), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL((k_tile_permute<S>), dim3(grid_of(a.ntiles)), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
