@@ -152,12 +152,22 @@ const char *sv_last_error(void);
 /* Smallest k routed to MFMA when SV_OPT_VARIANT is AUTO (default 4). */
 #define SV_OPT_MFMA_MIN_K 3
 
-/* Lazy relabel: 1 = a gate kernel may write its tile back with high targets
- * moved to low physical bits (L' = alpha o L, no extra traffic); 0 = never. */
+/* Lazy relabel (the single-GPU analogue of on-demand promotion, Section IV-D):
+ * 1 = when a fused gate has targets at physical bits >= SV_OPT_LOW_BITS, the
+ * MFMA sweep writes its tile back with those targets exchanged with low
+ * non-target bits of the same tile (L' = alpha o L, no extra traffic); the
+ * victims are chosen by SV_OPT_POLICY.  0 = never (default). */
 #define SV_OPT_LAZY_RELABEL 4
 
-/* Physical bits below this count as "low" for the relabel policy (default 5). */
+/* Physical bits below this count are the "frames" of the relabel policy (default 12). */
 #define SV_OPT_LOW_BITS 5
+
+/* Victim policy among eligible low bits (Corollary 1: farthest next use
+ * minimises promotions when the future is known). */
+#define SV_OPT_POLICY 7
+#define SV_POLICY_BELADY 0     /* farthest next use (hints from sv_hint_next_use), else LRU */
+#define SV_POLICY_FIRST_FREE 1 /* lowest-indexed eligible bit */
+#define SV_POLICY_LRU 2        /* least recently used qubit */
 
 /* Where the waves of a k <= 5 MFMA sweep keep the embedded gate operand:
  * in their own registers, or once per workgroup in LDS (default). */
@@ -168,15 +178,35 @@ const char *sv_last_error(void);
 int sv_set_option(sv_state *s, int key, int value);
 int sv_get_option(const sv_state *s, int key, int *value);
 
-/* Counters since sv_alloc/sv_reset: gate sweeps, swap half-sweeps, kernel launches. */
+/* Counters since sv_alloc/sv_reset. */
 typedef struct sv_stats {
-  int64_t gate_sweeps;
-  int64_t swap_half_sweeps;
-  int64_t relabels;
-  int64_t launches;
-  int64_t by_variant[5];
+  int64_t gate_sweeps;      /* fused-gate applications */
+  int64_t swap_half_sweeps; /* single bit-transposition passes (half of the state moves) */
+  int64_t relabels;         /* target bits moved down by the lazy relabel */
+  int64_t launches;         /* kernels launched by gate and layout calls */
+  int64_t by_variant[5];    /* gate applications per SV_VARIANT_* */
+  int64_t permute_sweeps;   /* full-sweep tile permutation passes */
 } sv_stats;
 int sv_get_stats(const sv_state *s, sv_stats *out);
+
+/*
+ * Planner hint for the relabel policy: next_use[q] = position in the caller's
+ * gate stream of the next gate that targets logical qubit q (INT64_MAX: none).
+ * Positions only need to be comparable between qubits.  Host int64[N],
+ * copied.  Without hints the BELADY policy behaves as LRU.
+ */
+int sv_hint_next_use(sv_state *s, const int64_t *next_use);
+
+/*
+ * Host-only simulation of the promotion policy in the all-frame demand model
+ * of Corollary 1: `frames` low positions hold logical qubits 0..frames-1
+ * initially; for each target tuple (concatenated, sizes ks[i] <= frames),
+ * every target not in a frame is promoted by evicting an eligible frame (one
+ * whose qubit is not in the current tuple) chosen by `policy`.  Returns the
+ * total number of promotions in *out.  No GPU involved.
+ */
+int sv_policy_simulate(int n_qubits, int frames, int policy, int n_tuples, const int32_t *ks,
+                       const int32_t *targets, int64_t *out);
 
 #ifdef __cplusplus
 }

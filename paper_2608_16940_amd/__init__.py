@@ -133,7 +133,16 @@ class StateVector:
         s = _native.sv_stats()
         check(lib().sv_get_stats(self._h, ctypes.byref(s)))
         return {"gate_sweeps": s.gate_sweeps, "swap_half_sweeps": s.swap_half_sweeps, "relabels": s.relabels,
-                "launches": s.launches, "by_variant": list(s.by_variant)}
+                "launches": s.launches, "by_variant": list(s.by_variant), "permute_sweeps": s.permute_sweeps}
+
+    def set_relabel(self, on: bool, low_bits: int = 12, policy: str = "belady"):
+        self.set_option(_native.OPT_LAZY_RELABEL, 1 if on else 0)
+        self.set_option(_native.OPT_LOW_BITS, int(low_bits))
+        self.set_option(_native.OPT_POLICY, _native.POLICY[policy])
+
+    def hint_next_use(self, next_use):
+        a = np.ascontiguousarray(np.asarray(next_use, dtype=np.int64))
+        check(lib().sv_hint_next_use(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
 
     def physical_state(self) -> np.ndarray:
         """Host copy of the stored amplitudes (physical order), complex128."""
@@ -153,6 +162,17 @@ def sample_probs(probs_dev, seed: int, shots: int, stream=None) -> np.ndarray:
                                 int(shots), out.ctypes.data_as(_native._u64p), ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel(), sp))
     return out
+
+
+def policy_simulate(n: int, frames: int, tuples, policy: str = "belady") -> int:
+    """Promotions made by a victim policy in the all-frame demand model (host only)."""
+    ks = np.array([len(t) for t in tuples], dtype=np.int32)
+    tg = np.array([q for t in tuples for q in t], dtype=np.int32)
+    out = ctypes.c_int64()
+    check(lib().sv_policy_simulate(int(n), int(frames), _native.POLICY[policy], len(tuples),
+                                   ks.ctypes.data_as(_native._i32p), tg.ctypes.data_as(_native._i32p),
+                                   ctypes.byref(out)))
+    return int(out.value)
 
 
 class Plan:

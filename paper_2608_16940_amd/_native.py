@@ -24,6 +24,8 @@ OPT_MFMA_MIN_K = 3
 OPT_LAZY_RELABEL = 4
 OPT_LOW_BITS = 5
 OPT_MFMA_OPERAND = 6
+OPT_POLICY = 7
+POLICY = {"belady": 0, "first_free": 1, "lru": 2}
 MFMA_OPERAND = {"regs": 0, "lds": 1}
 
 VARIANT = {"auto": 0, "valu": 1, "shuffle": 2, "mfma": 3, "generic": 4}
@@ -39,7 +41,7 @@ class SvError(RuntimeError):
 class sv_stats(ctypes.Structure):
     _fields_ = [("gate_sweeps", ctypes.c_int64), ("swap_half_sweeps", ctypes.c_int64),
                 ("relabels", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("by_variant", ctypes.c_int64 * 5)]
+                ("by_variant", ctypes.c_int64 * 5), ("permute_sweeps", ctypes.c_int64)]
 
 
 _lib = None
@@ -75,6 +77,9 @@ SIGNATURES = [
     ("sv_plan_block_matrix", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("sv_run_plan", ctypes.c_int, [_vp, _vp]),
     ("sv_plan_free", ctypes.c_int, [_vp]),
+    ("sv_hint_next_use", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+    ("sv_policy_simulate", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i32p,
+                                          ctypes.POINTER(ctypes.c_int64)]),
 ]
 
 

@@ -2,6 +2,8 @@
 // staging, probabilities, norm and sampling.  Host code only; kernels live in
 // sv_kernels.hip and sv_tile.hip.
 #include <algorithm>
+#include <climits>
+#include <utility>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -63,8 +65,14 @@ struct sv_state {
   int prec = SV_PREC_FP32;
   int mfma_min_k = 4;
   int lazy = 0;
-  int low_bits = 5;
+  int low_bits = 12;
+  int policy = SV_POLICY_BELADY;
   int opsrc = SV_MFMA_OPERAND_LDS;
+  // relabel policy state: planner hints and recency per logical qubit
+  bool have_hints = false;
+  int64_t next_use[64];
+  int64_t last_use[64];
+  int64_t clock = 0;
   // operand staging ring
   char *pinned = nullptr;
   hipEvent_t ev[kRingSlots];
@@ -78,7 +86,13 @@ namespace {
 bool valid_n(int n) { return n >= SV_MIN_QUBITS && n <= SV_MAX_QUBITS; }
 
 void reset_layout(sv_state *s) {
-  for (int q = 0; q < s->n; ++q) s->L[q] = s->Linv[q] = q;
+  for (int q = 0; q < s->n; ++q) {
+    s->L[q] = s->Linv[q] = q;
+    s->last_use[q] = 0;
+    s->next_use[q] = INT64_MAX;
+  }
+  s->clock = 0;
+  s->have_hints = false;
 }
 
 LayoutArg layout_arg(const sv_state *s) {
@@ -120,6 +134,57 @@ void swap_physical(sv_state *s, int p, int q) {
   s->Linv[q] = a;
 }
 
+// Victim choice among candidate physical positions (Corollary 1: farthest next
+// use; without hints, least recently used; FIRST_FREE: lowest position).
+// Ties go to the lowest physical position.
+int pick_victim(int policy, const std::vector<int> &cand, const int32_t *Linv, bool have_hints,
+                const int64_t *next_use, const int64_t *last_use) {
+  int best = -1;
+  for (int p : cand) {
+    if (best < 0) {
+      best = p;
+      continue;
+    }
+    const int q = Linv[p], qb = Linv[best];
+    bool better = false;
+    if (policy == SV_POLICY_FIRST_FREE) {
+      better = p < best;
+    } else if (policy == SV_POLICY_BELADY && have_hints) {
+      better = next_use[q] > next_use[qb] || (next_use[q] == next_use[qb] && p < best);
+    } else {
+      better = last_use[q] < last_use[qb] || (last_use[q] == last_use[qb] && p < best);
+    }
+    if (better) best = p;
+  }
+  return best;
+}
+
+// Lazy relabel plan for an MFMA sweep: targets at physical bits >= low_bits
+// are exchanged with victim low non-target bits inside the tile.  Victims are
+// drawn only from the tile's own non-target bits (the M lowest non-target
+// bits), leaving its three lowest ones alone, so the relabelling sweep keeps
+// exactly the access pattern of a plain sweep.  Returns the exchanged pairs.
+std::vector<std::pair<int, int>> plan_relabel(const sv_state *s, const int32_t *A, int k, int M) {
+  std::vector<std::pair<int, int>> pairs;
+  uint64_t tmask = 0;
+  for (int j = 0; j < k; ++j) tmask |= uint64_t(1) << A[j];
+  std::vector<int> cand;
+  int seen = 0;
+  for (int p = 0; p < s->n && seen < M; ++p) {
+    if ((tmask >> p) & 1) continue;
+    ++seen;
+    if (seen > 3 && p < s->low_bits) cand.push_back(p);
+  }
+  const int budget = M - 3;
+  for (int j = 0; j < k && int(pairs.size()) < budget; ++j) {
+    if (A[j] < s->low_bits || cand.empty()) continue;
+    const int v = pick_victim(s->policy, cand, s->Linv, s->have_hints, s->next_use, s->last_use);
+    cand.erase(std::find(cand.begin(), cand.end(), v));
+    pairs.push_back({A[j], v});
+  }
+  return pairs;
+}
+
 int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
   const int n = s->n;
   int v = s->variant;
@@ -157,9 +222,25 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
         return SV_ERR_UNSUPPORTED;
       }
       TilePlan tp;
-      if (!make_gate_tile(n, k, A, &tp)) {
+      std::vector<std::pair<int, int>> pairs;
+      if (s->lazy) pairs = plan_relabel(s, A, k, mfma_tile_M(k));
+      uint64_t extra = 0;
+      for (auto &pr : pairs) extra |= uint64_t(1) << pr.second;
+      if (!make_gate_tile(n, k, A, extra, &tp)) {
         set_error("tile geometry failed");
         return SV_ERR_UNSUPPORTED;
+      }
+      // store side: output tile-order bit of position a reads the local bit that
+      // held position v on load, and vice versa (a physical bit exchange)
+      for (auto &pr : pairs) {
+        int ba = -1, bv = -1;
+        for (int b = 0; b < tp.s; ++b) {
+          if (tp.sbit[b] == pr.first) ba = b;
+          if (tp.sbit[b] == pr.second) bv = b;
+        }
+        const int t = tp.loc_out[ba];
+        tp.loc_out[ba] = tp.loc_out[bv];
+        tp.loc_out[bv] = t;
       }
       std::vector<char> buf(mfma_operand_bytes(k, s->prec));
       pack_mfma_operand(k, s->prec, matrix, buf.data());
@@ -171,6 +252,8 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
       if (e == hipSuccess) {
         rc = release_slot(s, slot);
         if (rc) return rc;
+        for (auto &pr : pairs) swap_physical(s, pr.first, pr.second);
+        s->stats.relabels += int64_t(pairs.size());
       }
       break;
     }
@@ -322,7 +405,12 @@ int sv_apply_fused(sv_state *s, const double *matrix, const int32_t *targets, in
       }
     A[j] = s->L[targets[j]];
   }
-  return apply_physical(s, matrix, A, k);
+  const int rc = apply_physical(s, matrix, A, k);
+  if (rc == SV_OK) {
+    ++s->clock;
+    for (int j = 0; j < k; ++j) s->last_use[targets[j]] = s->clock;
+  }
+  return rc;
 }
 
 int sv_permute_layout(sv_state *s, const int32_t *new_layout) {
@@ -341,18 +429,146 @@ int sv_permute_layout(sv_state *s, const int32_t *new_layout) {
     seen[p] = true;
   }
   // Selection order: fill physical positions 0..n-1 with their final qubits,
-  // one bit transposition at a time (Lemma 2: each swap updates L = tau o L).
+  // one bit transposition at a time (Lemma 2: each exchange updates
+  // L = tau o L).  Consecutive disjoint transpositions commute, so several
+  // of them run as one in-place tile pass (one sweep) when the state has at
+  // least 12 qubits (five pairs at most, so that the tile always keeps physical
+  // bit 0); smaller states use single transposition passes.
+  int32_t L[64], Linv[64];
+  for (int q = 0; q < n; ++q) {
+    L[q] = s->L[q];
+    Linv[s->L[q]] = q;
+  }
+  std::vector<std::pair<int, int>> swaps;
   for (int p = 0; p < n; ++p) {
     int want = -1;
     for (int q = 0; q < n; ++q)
       if (new_layout[q] == p) want = q;
-    const int cur = s->L[want];
+    const int cur = L[want];
     if (cur == p) continue;
-    SV_HIP_CHECK(launch_swap_bits(s->amps, n, p, cur, s->st));
-    swap_physical(s, p, cur);
-    s->stats.swap_half_sweeps += 1;
-    s->stats.launches += 1;
+    swaps.push_back({p, cur});
+    const int a = Linv[p], b = Linv[cur];
+    L[a] = cur;
+    L[b] = p;
+    Linv[p] = b;
+    Linv[cur] = a;
   }
+  constexpr int kTileBits = 12;
+  size_t i = 0;
+  while (i < swaps.size()) {
+    if (n < kTileBits) {
+      SV_HIP_CHECK(launch_swap_bits(s->amps, n, swaps[i].first, swaps[i].second, s->st));
+      swap_physical(s, swaps[i].first, swaps[i].second);
+      s->stats.swap_half_sweeps += 1;
+      s->stats.launches += 1;
+      ++i;
+      continue;
+    }
+    uint64_t used = 0;
+    size_t j = i;
+    while (j < swaps.size() && j - i < 5) {
+      const uint64_t m = (uint64_t(1) << swaps[j].first) | (uint64_t(1) << swaps[j].second);
+      if (used & m) break;
+      used |= m;
+      ++j;
+    }
+    // tile: the exchanged bits plus the lowest other bits, 12 in total
+    uint64_t smask = used;
+    for (int p = 0; p < n && __builtin_popcountll(smask) < kTileBits; ++p) smask |= uint64_t(1) << p;
+    TilePlan tp;
+    tp.n = n;
+    tp.s = kTileBits;
+    int b = 0;
+    for (int p = 0; p < n; ++p)
+      if ((smask >> p) & 1) {
+        tp.sbit[b] = p;
+        tp.loc_in[b] = b;
+        tp.loc_out[b] = b;
+        ++b;
+      }
+    for (size_t t = i; t < j; ++t) {
+      int ba = -1, bb = -1;
+      for (int c = 0; c < tp.s; ++c) {
+        if (tp.sbit[c] == swaps[t].first) ba = c;
+        if (tp.sbit[c] == swaps[t].second) bb = c;
+      }
+      tp.loc_out[ba] = bb;
+      tp.loc_out[bb] = ba;
+    }
+    SV_HIP_CHECK(launch_tile_permute(tp, s->amps, s->st));
+    for (size_t t = i; t < j; ++t) swap_physical(s, swaps[t].first, swaps[t].second);
+    s->stats.permute_sweeps += 1;
+    s->stats.launches += 1;
+    i = j;
+  }
+  return SV_OK;
+}
+
+int sv_hint_next_use(sv_state *s, const int64_t *next_use) {
+  if (!s || !next_use) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  for (int q = 0; q < s->n; ++q) s->next_use[q] = next_use[q];
+  s->have_hints = true;
+  return SV_OK;
+}
+
+int sv_policy_simulate(int n, int frames, int policy, int n_tuples, const int32_t *ks, const int32_t *targets,
+                       int64_t *out) {
+  if (!out || n < 1 || n > 64 || frames < 1 || frames > n || n_tuples < 0 || (n_tuples > 0 && (!ks || !targets)) ||
+      policy < SV_POLICY_BELADY || policy > SV_POLICY_LRU) {
+    set_error("bad argument");
+    return SV_ERR_ARG;
+  }
+  std::vector<std::vector<int>> tup(static_cast<size_t>(n_tuples));
+  size_t off = 0;
+  for (int i = 0; i < n_tuples; ++i) {
+    if (ks[i] < 1 || ks[i] > frames) {
+      set_error("tuple wider than the frame count");
+      return SV_ERR_ARG;
+    }
+    for (int j = 0; j < ks[i]; ++j) {
+      const int q = targets[off + j];
+      if (q < 0 || q >= n) {
+        set_error("target out of range");
+        return SV_ERR_ARG;
+      }
+      tup[size_t(i)].push_back(q);
+    }
+    off += size_t(ks[i]);
+  }
+  // positions 0..frames-1 are frames; position of qubit q is L[q]
+  int32_t L[64], Linv[64];
+  int64_t last_use[64] = {0}, next_use[64];
+  for (int q = 0; q < n; ++q) L[q] = Linv[q] = q;
+  int64_t promotions = 0;
+  for (int i = 0; i < n_tuples; ++i) {
+    for (int q = 0; q < n; ++q) {
+      next_use[q] = INT64_MAX;
+      for (int t = i + 1; t < n_tuples; ++t)
+        if (std::find(tup[size_t(t)].begin(), tup[size_t(t)].end(), q) != tup[size_t(t)].end()) {
+          next_use[q] = t;
+          break;
+        }
+    }
+    for (int q : tup[size_t(i)]) {
+      if (L[q] < frames) continue;
+      std::vector<int> cand;
+      for (int p = 0; p < frames; ++p)
+        if (std::find(tup[size_t(i)].begin(), tup[size_t(i)].end(), Linv[p]) == tup[size_t(i)].end())
+          cand.push_back(p);
+      const int v = pick_victim(policy, cand, Linv, true, next_use, last_use);
+      const int a = q, b = Linv[v], pa = L[q];
+      L[a] = v;
+      L[b] = pa;
+      Linv[v] = a;
+      Linv[pa] = b;
+      ++promotions;
+    }
+    for (int q : tup[size_t(i)]) last_use[q] = i + 1;
+  }
+  *out = promotions;
   return SV_OK;
 }
 
@@ -465,8 +681,12 @@ int sv_set_option(sv_state *s, int key, int value) {
       s->lazy = value ? 1 : 0;
       return SV_OK;
     case SV_OPT_LOW_BITS:
-      if (value < 1 || value > 20) break;
+      if (value < 1 || value > 35) break;
       s->low_bits = value;
+      return SV_OK;
+    case SV_OPT_POLICY:
+      if (value < SV_POLICY_BELADY || value > SV_POLICY_LRU) break;
+      s->policy = value;
       return SV_OK;
     case SV_OPT_MFMA_OPERAND:
       if (value != SV_MFMA_OPERAND_REGS && value != SV_MFMA_OPERAND_LDS) break;
@@ -491,6 +711,7 @@ int sv_get_option(const sv_state *s, int key, int *value) {
     case SV_OPT_LAZY_RELABEL: *value = s->lazy; return SV_OK;
     case SV_OPT_LOW_BITS: *value = s->low_bits; return SV_OK;
     case SV_OPT_MFMA_OPERAND: *value = s->opsrc; return SV_OK;
+    case SV_OPT_POLICY: *value = s->policy; return SV_OK;
     default: break;
   }
   set_error("bad option key");

@@ -97,9 +97,11 @@ struct TilePlan {
 size_t mfma_operand_bytes(int K, int prec);
 void pack_mfma_operand(int K, int prec, const double *G, void *out);
 
-// Tile geometry for a dense gate on physical targets A (gate order).  Returns false
-// if the state is too small for the MFMA tiling.
-bool make_gate_tile(int n, int K, const int32_t *A, TilePlan *tp);
+// Tile geometry for a dense gate on physical targets A (gate order).  The
+// non-target tile bits are the bits of `extra` (which must not contain targets)
+// followed by the lowest other non-target bits, M in total.  Returns false if
+// the state is too small for the MFMA tiling.
+bool make_gate_tile(int n, int K, const int32_t *A, uint64_t extra, TilePlan *tp);
 int mfma_tile_M(int K);
 
 // opsrc: SV_MFMA_OPERAND_* (where k <= 5 waves keep the embedded operand).

@@ -2,6 +2,7 @@
 #include "sv_plan.h"
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -198,8 +199,20 @@ int sv_run_plan(sv_state *s, const sv_plan *p) {
     sv::set_error("null pointer");
     return SV_ERR_ARG;
   }
-  for (const SvBlock &b : p->blocks) {
-    const int rc = sv_apply_fused(s, b.matrix.data(), b.tuple.data(), b.k);
+  // next use of every logical qubit after each block: the relabel policy's
+  // view of the future (Corollary 1)
+  const size_t nb = p->blocks.size();
+  std::vector<int64_t> next(size_t(p->n), INT64_MAX);
+  std::vector<std::vector<int64_t>> hints(nb);
+  for (size_t i = nb; i-- > 0;) {
+    hints[i] = next;
+    for (int32_t q : p->blocks[i].tuple) next[size_t(q)] = int64_t(i);
+  }
+  for (size_t i = 0; i < nb; ++i) {
+    const SvBlock &b = p->blocks[i];
+    int rc = sv_hint_next_use(s, hints[i].data());
+    if (rc) return rc;
+    rc = sv_apply_fused(s, b.matrix.data(), b.tuple.data(), b.k);
     if (rc) return rc;
   }
   return SV_OK;

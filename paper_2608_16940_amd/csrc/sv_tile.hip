@@ -411,7 +411,7 @@ int mfma_tile_M(int K) {
   }
 }
 
-bool make_gate_tile(int n, int K, const int32_t *A, TilePlan *tp) {
+bool make_gate_tile(int n, int K, const int32_t *A, uint64_t extra, TilePlan *tp) {
   const int M = mfma_tile_M(K);
   if (M < 0 || n < K + M) return false;
   tp->n = n;
@@ -420,14 +420,18 @@ bool make_gate_tile(int n, int K, const int32_t *A, TilePlan *tp) {
   tp->s = K + M;
   uint64_t tmask = 0;
   for (int j = 0; j < K; ++j) tmask |= uint64_t(1) << A[j];
-  uint64_t lowmask = 0;
-  int got = 0;
+  if (extra & tmask) return false;
+  uint64_t lowmask = extra;
+  int got = __builtin_popcountll(extra);
+  if (got > M) return false;
   for (int p = 0; p < n && got < M; ++p)
-    if (!((tmask >> p) & 1)) {
+    if (!((tmask >> p) & 1) && !((lowmask >> p) & 1)) {
       lowmask |= uint64_t(1) << p;
       ++got;
     }
   tp->smask = tmask | lowmask;
+  // 16-byte chunks pair amplitudes that differ in physical bit 0: it must be a tile bit
+  if (!(tp->smask & 1)) return false;
   int b = 0, rank = 0;
   for (int p = 0; p < n; ++p) {
     if (!((tp->smask >> p) & 1)) continue;

@@ -1,0 +1,117 @@
+"""Full-size (N=30) checks in the launch configuration bench.py times.
+
+* the headline circuit (brickwork depth 24 + QFT30, greedy fusion k<=5)
+  against complex128 oracle amplitudes stored by
+  tests/golden/make_headline_n30_golden.py at 2050 seeded indices;
+* QFT30 of a basis state against its closed form at sampled indices;
+* echo: the fused circuit followed by its fused inverse returns |0...0>.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N = 30
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "headline_n30_amplitudes.txt")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2608_16940_amd as P
+    P.lib()
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def logical_to_physical(x, layout):
+    x = np.asarray(x, dtype=np.int64)
+    y = np.zeros_like(x)
+    for q, pos in enumerate(layout):
+        y |= ((x >> q) & 1) << int(pos)
+    return y
+
+
+def gather(sv, logical_idx):
+    import torch
+    phys = logical_to_physical(logical_idx, sv.layout())
+    sv.sync()
+    return sv.amps[torch.from_numpy(phys).to(sv.amps.device)].cpu().numpy().astype(np.complex128)
+
+
+def read_golden():
+    idx, vals, norm = [], [], None
+    with open(GOLDEN) as f:
+        for ln in f:
+            if ln.startswith("# norm"):
+                norm = float(ln.split()[2])
+            if ln.startswith("#") or not ln.strip():
+                continue
+            i, re, im = ln.split()
+            idx.append(int(i))
+            vals.append(complex(float(re), float(im)))
+    return np.array(idx, dtype=np.int64), np.array(vals, dtype=np.complex128), norm
+
+
+def test_headline_n30_against_oracle_samples(P):
+    idx, ref, onorm = read_golden()
+    assert abs(onorm - 1) < 1e-10
+    gates = W.headline(N, 24, 0)
+    plan = P.Plan.greedy(N, gates, 5)
+    sv = P.StateVector(N)
+    say("headline plan blocks", len(plan))
+    plan.run(sv)
+    got = gather(sv, idx)
+    d = np.abs(got - ref)
+    rel = float(np.sqrt(np.sum(d ** 2) / np.sum(np.abs(ref) ** 2)))
+    say("headline n30: max|d| %.3e  rel_l2(sample) %.3e  typical |amp| %.3e" % (d.max(), rel, np.abs(ref).mean()))
+    assert d.max() <= 1e-5
+    assert rel <= 1e-5
+    nrm = sv.norm()
+    assert abs(nrm - 1) <= 1e-5
+    sv.close()
+
+
+def test_qft30_basis_state_closed_form(P):
+    x = 0x2A5F1C3D & ((1 << N) - 1)
+    plan = P.Plan.greedy(N, W.basis_prep(N, x) + W.qft(N), 5)
+    sv = P.StateVector(N)
+    plan.run(sv)
+    rng = np.random.default_rng(7)
+    ys = np.unique(np.concatenate([rng.integers(0, 1 << N, 4096), [0, 1, (1 << N) - 1]]))
+    got = gather(sv, ys)
+    # phase = 2 pi x y / 2^N, reduced exactly in integers before the float conversion
+    ph = (np.uint64(x) * ys.astype(np.uint64)) & np.uint64((1 << N) - 1)
+    ref = np.exp(2j * np.pi * ph.astype(np.float64) / (1 << N)) / math.sqrt(1 << N)
+    d = np.abs(got - ref)
+    say("qft30: max|d| %.3e rel %.3e" % (d.max(), d.max() * math.sqrt(1 << N)))
+    assert d.max() <= 1e-5
+    assert d.max() * math.sqrt(1 << N) <= 1e-3  # relative to the amplitude magnitude
+    sv.close()
+
+
+def test_echo_n30(P):
+    gates = W.headline(N, 24, 0)
+    fwd = P.Plan.greedy(N, gates, 5)
+    inv = P.Plan.greedy(N, W.inverse(gates), 5)
+    sv = P.StateVector(N)
+    fwd.run(sv)
+    inv.run(sv)
+    a0 = gather(sv, np.array([0]))[0]
+    f0 = abs(a0) ** 2
+    say("echo n30: |<0|psi>|^2 = %.9f" % f0)
+    assert f0 >= 1 - 1e-5
+    s = sv.sample(99, 1000)
+    assert np.all(s == 0)
+    sv.close()

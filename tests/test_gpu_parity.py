@@ -262,3 +262,56 @@ def test_norm_and_probs(P):
     p = sv.probs(logical=True).cpu().numpy()
     np.testing.assert_allclose(p, np.abs(ref) ** 2, atol=1e-9)
     assert abs(sv.norm() - 1.0) < 1e-5
+
+
+# ---------------------------------------------------------------- lazy relabel (on-demand moves of high targets)
+@pytest.mark.parametrize("policy", ["belady", "first_free", "lru"])
+def test_relabel_keeps_logical_state(P, policy):
+    n = 17
+    gates = W.headline(n, 5, seed=3)
+    ref = oracle.run(n, gates)
+    sv = P.StateVector(n)
+    sv.set_relabel(True, low_bits=9, policy=policy)
+    plan = P.Plan.greedy(n, gates, 5)
+    plan.run(sv)
+    st = sv.stats()
+    say("relabel", policy, st)
+    assert st["relabels"] > 0
+    assert sorted(sv.layout().tolist()) == list(range(n))
+    check_close(ref, gpu_logical(sv), what=("relabel", policy))
+    # samples decode through the relabelled layout
+    s = sv.sample(5, 2000)
+    p_phys = sv.probs(logical=False).cpu().numpy()
+    np.testing.assert_array_equal(s, oracle.decode_index(oracle.sample(p_phys, 5, 2000), sv.layout()))
+    sv.canonicalize()
+    check_close(ref, sv.physical_state(), what=("relabel canonical", policy))
+
+
+def test_relabel_plain_calls_lru(P):
+    n = 16
+    rng = np.random.default_rng(31)
+    gates = rand_state_gates(n, rng, 1) + [W.random_dense(n, k, rng) for k in (4, 5, 6, 7, 5, 4, 5)]
+    ref = oracle.run(n, gates)
+    sv = P.StateVector(n)
+    sv.set_relabel(True, low_bits=8)
+    sv.apply_gates(gates)
+    check_close(ref, gpu_logical(sv), what="relabel plain")
+
+
+@pytest.mark.parametrize("n", [3, 8, 11, 12, 20])
+def test_permute_layout_small_and_tile_paths(P, n):
+    rng = np.random.default_rng(40 + n)
+    gates = rand_state_gates(n, rng, 2)
+    ref = oracle.run(n, gates)
+    sv = P.StateVector(n)
+    sv.apply_gates(gates)
+    for _ in range(2):
+        L = rng.permutation(n)
+        sv.permute_layout(L)
+        np.testing.assert_array_equal(sv.layout(), L)
+        check_close(ref, gpu_logical(sv), what=("perm", n))
+    st = sv.stats()
+    if n >= 12:
+        assert st["permute_sweeps"] > 0 and st["swap_half_sweeps"] == 0
+    else:
+        assert st["permute_sweeps"] == 0
