@@ -1,0 +1,75 @@
+/*
+ * libsv batched path: many small independent circuits in one persistent
+ * kernel launch (an addition to the paper's method, which applies one state
+ * at a time through the fused-operator interface of Section III R2; the gate
+ * semantics are the same).
+ *
+ * A circuit is a list of single-qubit gates (2x2 complex128 matrix, row-major
+ * interleaved) and CNOT gates (control, target) on n <= 18 qubits, applied to
+ * |0...0>.  Consecutive single-qubit gates on the same qubit are multiplied
+ * on the host in FP64 (later gate on the left, Section IV-C) before launch.
+ * Circuits with the same qubit count and the same gate structure (kinds and
+ * qubits, angles free) are grouped into packs of P that one workgroup runs in
+ * lockstep; P per qubit count comes from sv_batch_autotune or the caller.
+ * States of at most 2^14 amplitudes per pack slice stay in LDS for the whole
+ * circuit; larger states are updated in the caller's state buffer.
+ * Workgroups take packs from an atomic queue ordered by decreasing cost and
+ * exit when the queue is empty.
+ */
+#ifndef SV_BATCH_H_
+#define SV_BATCH_H_
+
+#include "sv.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SV_BATCH_MAX_QUBITS 18
+#define SV_BATCH_GATE_1Q 0
+#define SV_BATCH_GATE_CNOT 1
+
+typedef struct sv_batch_circuit {
+  int32_t n_qubits;     /* 1 .. SV_BATCH_MAX_QUBITS */
+  int32_t n_gates;
+  const int32_t *kinds;  /* n_gates entries: SV_BATCH_GATE_* */
+  const int32_t *qubits; /* 2 * n_gates entries: (q, unused) or (control, target) */
+  const double *mats;    /* 8 * n_gates doubles: 2x2 complex128 for 1q gates (ignored for CNOT) */
+} sv_batch_circuit;
+
+/* Per-qubit-count pack sizes: config[n] = circuits per workgroup for n qubits
+ * (a power of two, 1 <= config[n] <= 16, and config[n] * 2^n <= 2^14 when the
+ * state is to stay in LDS; larger n must use 1).  Index 0 is unused. */
+#define SV_BATCH_CONFIG_LEN (SV_BATCH_MAX_QUBITS + 1)
+
+/* Device workspace bytes for a batch (gate records, pack table, queue). */
+size_t sv_batch_workspace_bytes(int count, const sv_batch_circuit *circs);
+
+/*
+ * Run `count` circuits.  states_dev: device complex64 buffer of states_bytes
+ * bytes receiving every final state (circuit i at byte offset
+ * state_offsets[i], a host int64 array of multiples of 8; its 8 * 2^n_i bytes
+ * must lie inside the buffer; slices must not overlap).  z0_host:
+ * receives <Z_0> = sum_x |psi_x|^2 (1 - 2 x_0) per circuit, accumulated in
+ * FP64.  config: pack sizes (NULL = defaults).  Synchronises `stream`.
+ * Errors: SV_ERR_ARG (bad circuit or config, workspace too small).
+ */
+int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
+                 const int64_t *state_offsets, double *z0_host, const int32_t *config, void *ws_dev, size_t ws_bytes,
+                 void *stream);
+
+/*
+ * Pick config[n] for every qubit count present in the batch by timing each
+ * candidate pack size on a sample of up to `sample_per_size` circuits of that
+ * size (hipEvent timing, one warm-up).  Writes SV_BATCH_CONFIG_LEN entries to
+ * config_out and, if times_out is not NULL, the best time per circuit in
+ * seconds per qubit count.  Uses states_dev / ws_dev like sv_batch_run.
+ */
+int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
+                      const int64_t *state_offsets, int sample_per_size, int32_t *config_out, double *times_out,
+                      void *ws_dev, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_BATCH_H_ */

@@ -35,6 +35,37 @@ extern "C" {
 int sv_plan_greedy(int n_qubits, int n_gates, const int32_t *ks, const int32_t *targets, const double *mats,
                    const int8_t *diag, int k_max, sv_plan **out);
 
+/*
+ * Dynamic-programming fusion (Section IV-C, Eq. dp-recurrence): the gate list
+ * is cut into consecutive windows of `window` gates; inside a window
+ *   D_0 = 0,  D_i = min_{j in J_i} { D_j + Gamma(B(j, i)) },
+ * where B(j, i) is the block of gates j..i-1, J_i holds every j whose block
+ * width (distinct qubits) is within the cap for its mode (k_max for dense,
+ * diag_max for all-diagonal blocks) and always i-1 (an over-cap gate stays a
+ * singleton).  Backtracking gives the boundaries; a greedy pass then merges
+ * adjacent blocks across window boundaries when the merged block is within
+ * the cap and scores lower than the two apart.  No reordering.
+ *   score = SV_SCORE_PAPER:   Gamma = 4^k (dense), 1 (diagonal)
+ *   score = SV_SCORE_LEARNED: Gamma = exp(MLP(features)), the cost model's
+ *           predicted sweep time (sv_mlp.h), params host FP32 (nin, hid).
+ * Physical positions for the features are the logical qubits (identity
+ * layout at planning time).
+ */
+#define SV_SCORE_PAPER 0
+#define SV_SCORE_LEARNED 1
+int sv_plan_dp(int n_qubits, int n_gates, const int32_t *ks, const int32_t *targets, const double *mats,
+               const int8_t *diag, int k_max, int diag_max, int window, int score, const float *mlp_params_host,
+               int mlp_nin, int mlp_hid, sv_plan **out);
+
+/*
+ * Cost-model features of one fused sweep (SV_MLP_FEATURES floats): N/35,
+ * k/8, the k physical target positions sorted ascending divided by 35 and
+ * padded with -0.25 to seven slots, and the structural zero fraction of the
+ * block (1 - 2^-k when every gate is diagonal or a scaled permutation,
+ * else 0).  monomial: 1 if every gate has one non-zero per row.
+ */
+int sv_cost_features(int n_qubits, int k, const int32_t *phys_targets, int monomial, float *out);
+
 /* Number of fused blocks. */
 int sv_plan_num_blocks(const sv_plan *p, int *out);
 

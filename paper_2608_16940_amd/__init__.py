@@ -182,17 +182,40 @@ class Plan:
         self._h = handle
         self.n = n
 
-    @classmethod
-    def greedy(cls, n: int, gates, k_max: int = 5) -> "Plan":
+    @staticmethod
+    def _flat(gates):
         ks = np.array([len(g.targets) for g in gates], dtype=np.int32)
         tg = np.array([t for g in gates for t in g.targets], dtype=np.int32)
         mats = (np.concatenate([np.ascontiguousarray(g.matrix, dtype=np.complex128).reshape(-1) for g in gates])
                 .view(np.float64) if gates else np.zeros(0))
         dg = np.array([1 if getattr(g, "diag", False) else 0 for g in gates], dtype=np.int8)
+        return ks, tg, mats, dg
+
+    @classmethod
+    def greedy(cls, n: int, gates, k_max: int = 5) -> "Plan":
+        ks, tg, mats, dg = cls._flat(gates)
         h = ctypes.c_void_p()
         check(lib().sv_plan_greedy(int(n), len(gates), ks.ctypes.data_as(_native._i32p),
                                    tg.ctypes.data_as(_native._i32p), mats.ctypes.data_as(_native._dp),
                                    dg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), int(k_max), ctypes.byref(h)))
+        return cls(h, int(n))
+
+    @classmethod
+    def dp(cls, n: int, gates, k_max: int = 5, diag_max: int = 6, window: int = 64, params=None,
+           nin: int = 10, hid: int = 64) -> "Plan":
+        """Windowed DP fusion: paper score (params None) or learned sweep-time score (MLP params)."""
+        ks, tg, mats, dg = cls._flat(gates)
+        h = ctypes.c_void_p()
+        if params is None:
+            score, pp = 0, None
+        else:
+            score = 1
+            params = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+            pp = params.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        check(lib().sv_plan_dp(int(n), len(gates), ks.ctypes.data_as(_native._i32p),
+                               tg.ctypes.data_as(_native._i32p), mats.ctypes.data_as(_native._dp),
+                               dg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), int(k_max), int(diag_max),
+                               int(window), score, pp, int(nin), int(hid), ctypes.byref(h)))
         return cls(h, int(n))
 
     def __len__(self) -> int:

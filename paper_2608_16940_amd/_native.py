@@ -44,6 +44,14 @@ class sv_stats(ctypes.Structure):
                 ("by_variant", ctypes.c_int64 * 5), ("permute_sweeps", ctypes.c_int64)]
 
 
+class sv_batch_circuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
+                ("kinds", ctypes.POINTER(ctypes.c_int32)), ("qubits", ctypes.POINTER(ctypes.c_int32)),
+                ("mats", ctypes.POINTER(ctypes.c_double))]
+
+
+BATCH_CONFIG_LEN = 19
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -78,6 +86,26 @@ SIGNATURES = [
     ("sv_run_plan", ctypes.c_int, [_vp, _vp]),
     ("sv_plan_free", ctypes.c_int, [_vp]),
     ("sv_hint_next_use", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+    ("sv_mlp_param_count", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    ("sv_mlp_cache_floats", ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
+    ("sv_mlp_forward", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp]),
+    ("sv_mlp_backward", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                       _vp]),
+    ("sv_mlp_adam", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, _vp]),
+    ("sv_mlp_forward_host", ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_float), ctypes.c_int, _dp]),
+    ("sv_plan_dp", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, _dp, ctypes.POINTER(ctypes.c_int8),
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("sv_cost_features", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_float)]),
+    ("sv_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(sv_batch_circuit)]),
+    ("sv_batch_run", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(sv_batch_circuit), _vp, ctypes.c_size_t,
+                                    ctypes.POINTER(ctypes.c_int64), _dp, _i32p, _vp, ctypes.c_size_t, _vp]),
+    ("sv_batch_autotune", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(sv_batch_circuit), _vp, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _i32p, _dp, _vp,
+                                         ctypes.c_size_t, _vp]),
     ("sv_policy_simulate", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i32p,
                                           ctypes.POINTER(ctypes.c_int64)]),
 ]

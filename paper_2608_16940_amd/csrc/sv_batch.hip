@@ -1,0 +1,413 @@
+// Batched persistent kernel: thousands of small independent circuits in one
+// launch.  Each workgroup (512 threads) takes packs from an atomic queue; a
+// pack is P circuits with the same qubit count and gate structure, run in
+// lockstep by 512/P threads each.  States of up to 2^14 amplitudes per slice
+// live in LDS from |0...0> to the final write-back; larger states are updated
+// in place in the caller's buffer, which stays L2/MALL-resident (<= 2 MiB).
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "sv_batch.h"
+#include "sv_internal.h"
+
+namespace sv {
+namespace {
+
+constexpr int kBT = 512;             // threads per workgroup
+constexpr int kLdsAmps = 1 << 14;    // 128 KiB of complex64 state slices
+constexpr int kMaxPack = 16;
+
+struct BGate {
+  int32_t kind, q0, q1, pad;
+  float m[8];  // 2x2 complex64 row-major interleaved
+};
+
+struct BItem {
+  int32_t n, P, ngates, pad;  // ngates: longest circuit of the pack
+  int32_t circ[kMaxPack];
+  int32_t ngc[kMaxPack];      // gate count of each circuit
+  int64_t gate_off[kMaxPack];
+  int64_t state_off[kMaxPack];  // in amplitudes
+};
+
+__device__ __forceinline__ int64_t ins0(int64_t x, int p) {
+  const int64_t low = x & ((int64_t(1) << p) - 1);
+  return ((x >> p) << (p + 1)) | low;
+}
+
+__device__ __forceinline__ float2 cmad(float ar, float ai, float2 x, float2 acc) {
+  acc.x = fmaf(ar, x.x, acc.x);
+  acc.x = fmaf(-ai, x.y, acc.x);
+  acc.y = fmaf(ar, x.y, acc.y);
+  acc.y = fmaf(ai, x.x, acc.y);
+  return acc;
+}
+
+__global__ void k_batch_reset(unsigned *counter) {
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+__global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, int nitems,
+                                               const BGate *__restrict__ gates, float2 *__restrict__ states,
+                                               double *__restrict__ z0, unsigned *__restrict__ counter) {
+  __shared__ float2 lds[kLdsAmps];
+  __shared__ double red[kBT];
+  __shared__ int item_s;
+  const int tid = threadIdx.x;
+  while (true) {
+    if (tid == 0) item_s = int(atomicAdd(counter, 1u));
+    __syncthreads();
+    const int it = item_s;
+    __syncthreads();  // every thread has read item_s before it is overwritten
+    if (it >= nitems) break;  // uniform: all waves leave together
+    const BItem &I = items[it];
+    const int n = I.n, P = I.P, ngates = I.ngates;
+    const int Tc = kBT / P;
+    const int c = tid / Tc, lt = tid % Tc;
+    const int64_t dim = int64_t(1) << n;
+    const bool in_lds = int64_t(P) * dim <= kLdsAmps;
+    float2 *st = in_lds ? lds + int64_t(c) * dim : states + I.state_off[c];
+    const BGate *gl = gates + I.gate_off[c];
+    const int my_ng = I.ngc[c];
+
+    for (int64_t x = lt; x < dim; x += Tc) st[x] = make_float2(x == 0 ? 1.f : 0.f, 0.f);
+    __syncthreads();
+    // lockstep over the pack: a circuit past its last gate only meets the barriers
+    for (int g = 0; g < ngates; ++g) {
+      BGate G;
+      G.kind = -1;
+      if (g < my_ng) G = gl[g];
+      if (G.kind == SV_BATCH_GATE_1Q) {
+        const int q = G.q0;
+        for (int64_t p = lt; p < dim / 2; p += Tc) {
+          const int64_t x = ins0(p, q), y = x | (int64_t(1) << q);
+          const float2 a = st[x], b = st[y];
+          float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
+          o0 = cmad(G.m[0], G.m[1], a, o0);
+          o0 = cmad(G.m[2], G.m[3], b, o0);
+          o1 = cmad(G.m[4], G.m[5], a, o1);
+          o1 = cmad(G.m[6], G.m[7], b, o1);
+          st[x] = o0;
+          st[y] = o1;
+        }
+      } else if (G.kind == SV_BATCH_GATE_CNOT) {
+        const int cq = G.q0, tq = G.q1;
+        const int lo = cq < tq ? cq : tq, hi = cq < tq ? tq : cq;
+        for (int64_t p = lt; p < dim / 4; p += Tc) {
+          const int64_t x = ins0(ins0(p, lo), hi) | (int64_t(1) << cq);
+          const int64_t y = x | (int64_t(1) << tq);
+          const float2 a = st[x];
+          st[x] = st[y];
+          st[y] = a;
+        }
+      }
+      __syncthreads();
+    }
+    // <Z_0> in FP64 over this circuit's slice
+    double s = 0.0;
+    for (int64_t x = lt; x < dim; x += Tc) {
+      const float2 a = st[x];
+      const double pr = double(a.x) * double(a.x) + double(a.y) * double(a.y);
+      s += (x & 1) ? -pr : pr;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int w = Tc / 2; w > 0; w >>= 1) {
+      if (lt < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (lt == 0) z0[I.circ[c]] = red[tid];
+    if (in_lds) {
+      float2 *out = states + I.state_off[c];
+      for (int64_t x = lt; x < dim; x += Tc) out[x] = st[x];
+    }
+    __syncthreads();
+  }
+}
+
+struct Packed {
+  std::vector<BGate> gates;
+  std::vector<BItem> items;
+  int ncirc = 0;
+};
+
+bool valid_config(const int32_t *cfg) {
+  for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
+    const int P = cfg[n];
+    if (P < 1 || P > kMaxPack || (P & (P - 1))) return false;
+    if (P > 1 && (int64_t(P) << n) > kLdsAmps) return false;
+  }
+  return true;
+}
+
+void default_config(int32_t *cfg) {
+  cfg[0] = 1;
+  for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
+    int P = 1;
+    while (P < kMaxPack && (int64_t(P * 2) << n) <= kLdsAmps) P *= 2;
+    cfg[n] = (n <= 14) ? P : 1;
+  }
+}
+
+// Validate, fuse adjacent single-qubit gates on the same qubit (FP64, later
+// gate on the left), group by qubit count, sort each group by gate count so
+// that packs hold circuits of similar length, cut packs, order by cost.
+int pack_batch(int count, const sv_batch_circuit *circs, size_t states_bytes, const int64_t *state_offsets,
+               const int32_t *cfg, Packed *out) {
+  std::vector<std::vector<BGate>> fused(static_cast<size_t>(count));
+  std::map<int, std::vector<int>> groups;
+  for (int i = 0; i < count; ++i) {
+    const sv_batch_circuit &C = circs[i];
+    if (C.n_qubits < 1 || C.n_qubits > SV_BATCH_MAX_QUBITS || C.n_gates < 0 ||
+        (C.n_gates > 0 && (!C.kinds || !C.qubits)) || state_offsets[i] < 0 || (state_offsets[i] & 7) ||
+        uint64_t(state_offsets[i]) + (uint64_t(8) << C.n_qubits) > uint64_t(states_bytes)) {
+      set_error("bad batch circuit " + std::to_string(i));
+      return SV_ERR_ARG;
+    }
+    std::vector<BGate> &g = fused[size_t(i)];
+    double cur[8];
+    int cur_q = -1;
+    auto flush = [&]() {
+      if (cur_q < 0) return;
+      BGate b;
+      b.kind = SV_BATCH_GATE_1Q;
+      b.q0 = cur_q;
+      b.q1 = -1;
+      b.pad = 0;
+      for (int e = 0; e < 8; ++e) b.m[e] = float(cur[e]);
+      g.push_back(b);
+      cur_q = -1;
+    };
+    for (int j = 0; j < C.n_gates; ++j) {
+      const int kind = C.kinds[j];
+      const int q0 = C.qubits[2 * j], q1 = C.qubits[2 * j + 1];
+      if (kind == SV_BATCH_GATE_1Q) {
+        if (q0 < 0 || q0 >= C.n_qubits || !C.mats) {
+          set_error("bad single-qubit gate in batch circuit " + std::to_string(i));
+          return SV_ERR_ARG;
+        }
+        const double *m = C.mats + 8 * size_t(j);
+        if (cur_q == q0) {
+          // cur <- m * cur
+          double r[8];
+          for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+              double re = 0, im = 0;
+              for (int k = 0; k < 2; ++k) {
+                const double xr = m[2 * (2 * a + k)], xi = m[2 * (2 * a + k) + 1];
+                const double yr = cur[2 * (2 * k + b)], yi = cur[2 * (2 * k + b) + 1];
+                re += xr * yr - xi * yi;
+                im += xr * yi + xi * yr;
+              }
+              r[2 * (2 * a + b)] = re;
+              r[2 * (2 * a + b) + 1] = im;
+            }
+          std::memcpy(cur, r, sizeof(r));
+        } else {
+          flush();
+          std::memcpy(cur, m, sizeof(cur));
+          cur_q = q0;
+        }
+      } else if (kind == SV_BATCH_GATE_CNOT) {
+        if (q0 < 0 || q1 < 0 || q0 >= C.n_qubits || q1 >= C.n_qubits || q0 == q1) {
+          set_error("bad CNOT in batch circuit " + std::to_string(i));
+          return SV_ERR_ARG;
+        }
+        flush();
+        BGate b;
+        std::memset(&b, 0, sizeof(b));
+        b.kind = SV_BATCH_GATE_CNOT;
+        b.q0 = q0;
+        b.q1 = q1;
+        g.push_back(b);
+      } else {
+        set_error("unknown gate kind in batch circuit " + std::to_string(i));
+        return SV_ERR_ARG;
+      }
+    }
+    flush();
+    groups[C.n_qubits].push_back(i);
+  }
+  out->ncirc = count;
+  std::vector<int64_t> gate_off(static_cast<size_t>(count));
+  for (int i = 0; i < count; ++i) {
+    gate_off[size_t(i)] = int64_t(out->gates.size());
+    out->gates.insert(out->gates.end(), fused[size_t(i)].begin(), fused[size_t(i)].end());
+  }
+  std::vector<std::pair<double, BItem>> items;
+  for (auto &kv : groups) {
+    std::vector<int> ids = kv.second;
+    const int n = kv.first;
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int a, int b) { return fused[size_t(a)].size() > fused[size_t(b)].size(); });
+    size_t pos = 0;
+    while (pos < ids.size()) {
+      int P = cfg[n];
+      while (size_t(P) > ids.size() - pos) P /= 2;
+      BItem it;
+      std::memset(&it, 0, sizeof(it));
+      it.n = n;
+      it.P = P;
+      int ng = 0;
+      for (int c = 0; c < P; ++c) {
+        const int id = ids[pos + size_t(c)];
+        it.circ[c] = id;
+        it.ngc[c] = int(fused[size_t(id)].size());
+        ng = std::max(ng, it.ngc[c]);
+        it.gate_off[c] = gate_off[size_t(id)];
+        it.state_off[c] = state_offsets[id] / 8;
+      }
+      it.ngates = ng;
+      pos += size_t(P);
+      const double cost = double(ng + 1) * double(int64_t(1) << n) * double(P);
+      items.push_back({cost, it});
+    }
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<double, BItem> &a, const std::pair<double, BItem> &b) { return a.first > b.first; });
+  for (auto &pr : items) out->items.push_back(pr.second);
+  return SV_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int run_packed(const Packed &pk, void *states_dev, double *z0_dev_or_null, double *z0_host, void *ws_dev,
+               size_t ws_bytes, hipStream_t st, float *ms_out) {
+  const size_t o_cnt = 0;
+  const size_t o_z0 = 256;
+  const size_t o_items = o_z0 + align256(sizeof(double) * size_t(std::max(1, pk.ncirc)));
+  const size_t o_gates = o_items + align256(sizeof(BItem) * std::max<size_t>(1, pk.items.size()));
+  const size_t need = o_gates + align256(sizeof(BGate) * std::max<size_t>(1, pk.gates.size()));
+  if (ws_bytes < need) {
+    set_error("batch workspace too small");
+    return SV_ERR_ARG;
+  }
+  char *ws = static_cast<char *>(ws_dev);
+  unsigned *counter = reinterpret_cast<unsigned *>(ws + o_cnt);
+  double *z0 = z0_dev_or_null ? z0_dev_or_null : reinterpret_cast<double *>(ws + o_z0);
+  BItem *items = reinterpret_cast<BItem *>(ws + o_items);
+  BGate *gates = reinterpret_cast<BGate *>(ws + o_gates);
+  if (!pk.items.empty())
+    SV_HIP_CHECK(hipMemcpyAsync(items, pk.items.data(), sizeof(BItem) * pk.items.size(), hipMemcpyHostToDevice, st));
+  if (!pk.gates.empty())
+    SV_HIP_CHECK(hipMemcpyAsync(gates, pk.gates.data(), sizeof(BGate) * pk.gates.size(), hipMemcpyHostToDevice, st));
+  int dev = 0, cus = 256;
+  SV_HIP_CHECK(hipGetDevice(&dev));
+  SV_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms_out) {
+    SV_HIP_CHECK(hipEventCreate(&e0));
+    SV_HIP_CHECK(hipEventCreate(&e1));
+  }
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+  SV_HIP_CHECK(hipGetLastError());
+  if (ms_out) SV_HIP_CHECK(hipEventRecord(e0, st));
+  const int grid = std::max(1, std::min<int>(cus, int(pk.items.size())));
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), 0, st, items, int(pk.items.size()), gates,
+                     static_cast<float2 *>(states_dev), z0, counter);
+  SV_HIP_CHECK(hipGetLastError());
+  if (ms_out) SV_HIP_CHECK(hipEventRecord(e1, st));
+  if (z0_host && pk.ncirc > 0)
+    SV_HIP_CHECK(hipMemcpyAsync(z0_host, z0, sizeof(double) * size_t(pk.ncirc), hipMemcpyDeviceToHost, st));
+  SV_HIP_CHECK(hipStreamSynchronize(st));
+  if (ms_out) {
+    SV_HIP_CHECK(hipEventElapsedTime(ms_out, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return SV_OK;
+}
+
+}  // namespace
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+size_t sv_batch_workspace_bytes(int count, const sv_batch_circuit *circs) {
+  if (count < 0 || (count > 0 && !circs)) return 0;
+  size_t ng = 0;
+  for (int i = 0; i < count; ++i) ng += size_t(std::max(0, circs[i].n_gates));
+  return 256 + align256(sizeof(double) * size_t(std::max(1, count))) +
+         align256(sizeof(BItem) * size_t(std::max(1, count))) + align256(sizeof(BGate) * std::max<size_t>(1, ng));
+}
+
+int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
+                 const int64_t *state_offsets, double *z0_host, const int32_t *config, void *ws_dev, size_t ws_bytes,
+                 void *stream) {
+  if (count < 0 || (count > 0 && (!circs || !states_dev || !state_offsets || !z0_host)) || !ws_dev) {
+    set_error("bad batch argument");
+    return SV_ERR_ARG;
+  }
+  int32_t cfg[SV_BATCH_CONFIG_LEN];
+  if (config) {
+    std::memcpy(cfg, config, sizeof(cfg));
+    if (!valid_config(cfg)) {
+      set_error("bad batch config");
+      return SV_ERR_ARG;
+    }
+  } else {
+    default_config(cfg);
+  }
+  Packed pk;
+  int rc = pack_batch(count, circs, states_bytes, state_offsets, cfg, &pk);
+  if (rc) return rc;
+  return run_packed(pk, states_dev, nullptr, z0_host, ws_dev, ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
+                      const int64_t *state_offsets, int sample_per_size, int32_t *config_out, double *times_out,
+                      void *ws_dev, size_t ws_bytes, void *stream) {
+  if (count < 0 || (count > 0 && (!circs || !states_dev || !state_offsets)) || !config_out || !ws_dev ||
+      sample_per_size < 1) {
+    set_error("bad autotune argument");
+    return SV_ERR_ARG;
+  }
+  int32_t cfg[SV_BATCH_CONFIG_LEN];
+  default_config(cfg);
+  if (times_out)
+    for (int n = 0; n < SV_BATCH_CONFIG_LEN; ++n) times_out[n] = 0.0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
+    std::vector<sv_batch_circuit> sample;
+    std::vector<int64_t> offs;
+    for (int i = 0; i < count && int(sample.size()) < sample_per_size; ++i)
+      if (circs[i].n_qubits == n) {
+        sample.push_back(circs[i]);
+        offs.push_back(state_offsets[i]);
+      }
+    if (sample.empty()) continue;
+    std::vector<double> z(sample.size());
+    double best_t = 1e300;
+    int best_p = 1;
+    for (int P = 1; P <= kMaxPack; P *= 2) {
+      if (P > 1 && (int64_t(P) << n) > kLdsAmps) break;
+      int32_t trial[SV_BATCH_CONFIG_LEN];
+      std::memcpy(trial, cfg, sizeof(trial));
+      trial[n] = P;
+      Packed pk;
+      int rc = pack_batch(int(sample.size()), sample.data(), states_bytes, offs.data(), trial, &pk);
+      if (rc) return rc;
+      float ms = 0.f;
+      rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);  // warm-up
+      if (rc) return rc;
+      rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);
+      if (rc) return rc;
+      const double t = double(ms) * 1e-3 / double(sample.size());
+      if (t < best_t) {
+        best_t = t;
+        best_p = P;
+      }
+    }
+    cfg[n] = best_p;
+    if (times_out) times_out[n] = best_t;
+  }
+  std::memcpy(config_out, cfg, sizeof(cfg));
+  return SV_OK;
+}
+
+}  // extern "C"

@@ -87,33 +87,38 @@ __global__ __launch_bounds__(kThreads) void k_dense_valu(float2 *__restrict__ ps
 // bit 0 the pair is inside the lane; for bit b in 1..6 the partner pair sits
 // in lane (lane ^ 2^(b-1)) of the same wave and arrives by a cross-lane
 // shuffle, so every load and store of the wave is one contiguous 1 KiB run.
+// The grid is capped (a dispatch holds at most 2^32 - 1 work-items), so each
+// workgroup strides over chunk blocks; the stride is uniform per workgroup, so
+// whole waves stay together for the exchange.
 __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ psi4, int64_t nchunks, int b,
                                                          float2 m00, float2 m01, float2 m10, float2 m11) {
-  const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  const bool active = t < nchunks;
-  float4 v = active ? psi4[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-  float2 a0 = make_float2(v.x, v.y), a1 = make_float2(v.z, v.w);
-  float2 o0, o1;
-  if (b == 0) {
-    o0 = cfma(m01, a1, cmul(m00, a0));
-    o1 = cfma(m11, a1, cmul(m10, a0));
-  } else {
-    const int mask = 1 << (b - 1);
-    float4 p;
-    p.x = __shfl_xor(v.x, mask);
-    p.y = __shfl_xor(v.y, mask);
-    p.z = __shfl_xor(v.z, mask);
-    p.w = __shfl_xor(v.w, mask);
-    const float2 p0 = make_float2(p.x, p.y), p1 = make_float2(p.z, p.w);
-    if ((t >> (b - 1)) & 1) {  // this lane's amplitudes have bit b = 1; partners have bit b = 0
-      o0 = cfma(m11, a0, cmul(m10, p0));
-      o1 = cfma(m11, a1, cmul(m10, p1));
+  for (int64_t blk = int64_t(blockIdx.x) * kThreads; blk < nchunks; blk += int64_t(gridDim.x) * kThreads) {
+    const int64_t t = blk + threadIdx.x;
+    const bool active = t < nchunks;
+    float4 v = active ? psi4[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 a0 = make_float2(v.x, v.y), a1 = make_float2(v.z, v.w);
+    float2 o0, o1;
+    if (b == 0) {
+      o0 = cfma(m01, a1, cmul(m00, a0));
+      o1 = cfma(m11, a1, cmul(m10, a0));
     } else {
-      o0 = cfma(m01, p0, cmul(m00, a0));
-      o1 = cfma(m01, p1, cmul(m00, a1));
+      const int mask = 1 << (b - 1);
+      float4 p;
+      p.x = __shfl_xor(v.x, mask);
+      p.y = __shfl_xor(v.y, mask);
+      p.z = __shfl_xor(v.z, mask);
+      p.w = __shfl_xor(v.w, mask);
+      const float2 p0 = make_float2(p.x, p.y), p1 = make_float2(p.z, p.w);
+      if ((t >> (b - 1)) & 1) {  // this lane's amplitudes have bit b = 1; partners have bit b = 0
+        o0 = cfma(m11, a0, cmul(m10, p0));
+        o1 = cfma(m11, a1, cmul(m10, p1));
+      } else {
+        o0 = cfma(m01, p0, cmul(m00, a0));
+        o1 = cfma(m01, p1, cmul(m00, a1));
+      }
     }
+    if (active) psi4[t] = make_float4(o0.x, o0.y, o1.x, o1.y);
   }
-  if (active) psi4[t] = make_float4(o0.x, o0.y, o1.x, o1.y);
 }
 
 // ------------------------------------------------------------------ generic, any k <= 8
@@ -232,24 +237,28 @@ __device__ __forceinline__ uint64_t q_at(const float2 *psi, const double *probs,
   return fixed_q(psi ? prob_of(psi[i]) : probs[i]);
 }
 
-// One workgroup per 2^10-entry block: exact block total.
+// Exact total of each 2^10-entry block; workgroups stride over blocks (the
+// grid is capped below the 2^32 work-item limit of one dispatch).
 __global__ __launch_bounds__(kThreads) void k_block_totals(const float2 *__restrict__ psi,
-                                                           const double *__restrict__ probs, int64_t dim,
+                                                           const double *__restrict__ probs, int64_t dim, int64_t nb,
                                                            uint64_t *__restrict__ blocksum) {
   __shared__ uint64_t red[kThreads];
-  const int64_t b0 = int64_t(blockIdx.x) << kCdfBlockBits;
-  uint64_t s = 0;
-  for (int i = threadIdx.x; i < (1 << kCdfBlockBits); i += kThreads) {
-    const int64_t x = b0 + i;
-    if (x < dim) s += q_at(psi, probs, x);
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+    const int64_t b0 = blk << kCdfBlockBits;
+    uint64_t s = 0;
+    for (int i = threadIdx.x; i < (1 << kCdfBlockBits); i += kThreads) {
+      const int64_t x = b0 + i;
+      if (x < dim) s += q_at(psi, probs, x);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) blocksum[blk] = red[0];
     __syncthreads();
   }
-  if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0];
 }
 
 // Inclusive scan of 1024-element chunks in place (256 threads x 4), chunk total out.
@@ -446,8 +455,8 @@ hipError_t launch_dense_valu(float2 *psi, int n, int k, const int32_t *A, const 
 hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStream_t st) {
   if (n < 1 || b < 0 || b > 6 || b >= n) return hipErrorInvalidValue;
   const int64_t nchunks = int64_t(1) << (n - 1);
-  const int64_t blocks = (nchunks + kThreads - 1) / kThreads;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  int64_t blocks = (nchunks + kThreads - 1) / kThreads;
+  if (blocks > (int64_t(1) << 22)) blocks = int64_t(1) << 22;
   hipLaunchKernelGGL(k_1q_shuffle, dim3(unsigned(blocks)), dim3(kThreads), 0, st,
                      reinterpret_cast<float4 *>(psi), nchunks, b, m[0], m[1], m[2], m[3]);
   return hipGetLastError();
@@ -503,7 +512,8 @@ hipError_t launch_norm(const float2 *psi, int n, double *partials, double *resul
 hipError_t launch_cdf_build(const float2 *psi, const double *probs, int n, const Workspace &ws, hipStream_t st) {
   const int64_t dim = int64_t(1) << n;
   const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
-  hipLaunchKernelGGL(k_block_totals, dim3(unsigned(nb)), dim3(kThreads), 0, st, psi, probs, dim, ws.blocksum);
+  const int64_t gb = nb < (int64_t(1) << 20) ? nb : (int64_t(1) << 20);
+  hipLaunchKernelGGL(k_block_totals, dim3(unsigned(gb)), dim3(kThreads), 0, st, psi, probs, dim, nb, ws.blocksum);
   const int64_t nc = (nb + 1023) / 1024;
   hipLaunchKernelGGL(k_scan_chunks, dim3(unsigned(nc)), dim3(kThreads), 0, st, ws.blocksum, nb, ws.chunksum);
   if (nc > 1) {

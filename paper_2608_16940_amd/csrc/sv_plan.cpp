@@ -3,9 +3,13 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
+
+#include "sv_mlp.h"
 
 namespace sv {
 void set_error(const std::string &msg);
@@ -31,7 +35,21 @@ struct GateView {
   const int32_t *t;
   const double *m;
   bool diag;
+  bool monomial;  // one non-zero per row (diagonal or scaled permutation)
 };
+
+bool is_monomial(const double *m, int k) {
+  const int d = 1 << k;
+  double mx = 0;
+  for (int i = 0; i < d * d; ++i) mx = std::max(mx, std::hypot(m[2 * i], m[2 * i + 1]));
+  for (int r = 0; r < d; ++r) {
+    int nz = 0;
+    for (int c = 0; c < d; ++c)
+      if (std::hypot(m[2 * (r * d + c)], m[2 * (r * d + c) + 1]) > 1e-12 * mx) ++nz;
+    if (nz != 1) return false;
+  }
+  return true;
+}
 
 // M <- E(g) M, where E(g) is gate g embedded into the block's k-qubit space:
 // each column of M is a k-qubit vector and g acts on the local positions of
@@ -107,7 +125,7 @@ bool parse_gates(int n, int ngates, const int32_t *ks, const int32_t *targets, c
       for (int a = 0; a < j; ++a)
         if (t[a] == t[j]) return false;
     }
-    out->push_back(GateView{k, t, mats + moff, diag ? diag[i] != 0 : false});
+    out->push_back(GateView{k, t, mats + moff, diag ? diag[i] != 0 : false, is_monomial(mats + moff, k)});
     toff += size_t(k);
     moff += size_t(2) << (2 * k);
   }
@@ -223,4 +241,149 @@ int sv_plan_free(sv_plan *p) {
   return SV_OK;
 }
 
+int sv_cost_features(int n, int k, const int32_t *A, int monomial, float *out) {
+  if (!A || !out || k < 1 || k > 7 || n < 1 || n > SV_MAX_QUBITS) {
+    sv::set_error("bad feature argument");
+    return SV_ERR_ARG;
+  }
+  int s[7];
+  for (int j = 0; j < k; ++j) s[j] = A[j];
+  std::sort(s, s + k);
+  out[0] = float(n) / 35.f;
+  out[1] = float(k) / 8.f;
+  for (int j = 0; j < 7; ++j) out[2 + j] = (j < k) ? float(s[j]) / 35.f : -0.25f;
+  out[9] = monomial ? float(1.0 - std::ldexp(1.0, -k)) : 0.f;
+  return SV_OK;
+}
+
 }  // extern "C"
+
+namespace {
+
+struct Scorer {
+  int score;
+  int n;
+  const float *params;
+  int nin, hid;
+  std::map<std::vector<int32_t>, double> cache;  // (k, mono, sorted targets...) -> Gamma
+
+  double operator()(const std::vector<int32_t> &tuple_sorted, bool all_diag, bool all_mono) {
+    const int k = int(tuple_sorted.size());
+    if (score == SV_SCORE_PAPER) return all_diag ? 1.0 : std::ldexp(1.0, 2 * k);
+    if (k > 7) return 1e30;
+    std::vector<int32_t> key(tuple_sorted);
+    key.push_back(all_mono ? 1 : 0);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    float f[SV_MLP_FEATURES];
+    sv_cost_features(n, k, tuple_sorted.data(), all_mono ? 1 : 0, f);
+    double y = 0;
+    sv_mlp_forward_host(params, nin, hid, f, 1, &y);
+    const double g = std::exp(y);
+    cache.emplace(std::move(key), g);
+    return g;
+  }
+};
+
+struct Span {
+  size_t a, b;  // gates [a, b)
+};
+
+void span_info(const std::vector<GateView> &gates, size_t a, size_t b, std::vector<int32_t> *tuple, bool *diag,
+               bool *mono) {
+  tuple->clear();
+  *diag = true;
+  *mono = true;
+  for (size_t g = a; g < b; ++g) {
+    for (int j = 0; j < gates[g].k; ++j)
+      if (std::find(tuple->begin(), tuple->end(), gates[g].t[j]) == tuple->end()) tuple->push_back(gates[g].t[j]);
+    *diag = *diag && gates[g].diag;
+    *mono = *mono && gates[g].monomial;
+  }
+  std::sort(tuple->begin(), tuple->end());
+}
+
+}  // namespace
+
+extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
+                          const int8_t *diag, int k_max, int diag_max, int window, int score,
+                          const float *mlp_params, int mlp_nin, int mlp_hid, sv_plan **out) {
+  if (!out || ngates < 0 || (ngates > 0 && (!ks || !targets || !mats)) || k_max < 1 || k_max > 8 ||
+      diag_max < 1 || diag_max > 8 || window < 1 || n < SV_MIN_QUBITS || n > SV_MAX_QUBITS ||
+      (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED) ||
+      (score == SV_SCORE_LEARNED && (!mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1))) {
+    sv::set_error("bad dp planner argument");
+    return SV_ERR_ARG;
+  }
+  std::vector<GateView> gates;
+  if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
+    sv::set_error("bad gate in list");
+    return SV_ERR_ARG;
+  }
+  Scorer gamma{score, n, mlp_params, mlp_nin, mlp_hid, {}};
+  const int cap_any = std::max(k_max, diag_max);
+  std::vector<Span> spans;
+  std::vector<int32_t> tuple;
+  for (size_t w0 = 0; w0 < gates.size(); w0 += size_t(window)) {
+    const size_t h = std::min(size_t(window), gates.size() - w0);
+    std::vector<double> D(h + 1, 0.0);
+    std::vector<size_t> arg(h + 1, 0);
+    for (size_t i = 1; i <= h; ++i) {
+      double best = 1e300;
+      size_t bj = i - 1;
+      std::vector<int32_t> set;
+      bool all_diag = true, all_mono = true;
+      for (size_t j = i; j-- > 0;) {
+        const GateView &g = gates[w0 + j];
+        for (int q = 0; q < g.k; ++q)
+          if (std::find(set.begin(), set.end(), g.t[q]) == set.end()) set.push_back(g.t[q]);
+        all_diag = all_diag && g.diag;
+        all_mono = all_mono && g.monomial;
+        const int width = int(set.size());
+        const int cap = all_diag ? diag_max : k_max;
+        if (width <= cap || j == i - 1) {
+          std::vector<int32_t> srt(set);
+          std::sort(srt.begin(), srt.end());
+          const double c = D[j] + gamma(srt, all_diag, all_mono);
+          if (c < best) {
+            best = c;
+            bj = j;
+          }
+        }
+        if (width > cap_any) break;
+      }
+      D[i] = best;
+      arg[i] = bj;
+    }
+    std::vector<Span> win;
+    for (size_t i = h; i > 0; i = arg[i]) win.push_back(Span{w0 + arg[i], w0 + i});
+    std::reverse(win.begin(), win.end());
+    spans.insert(spans.end(), win.begin(), win.end());
+  }
+  // cross-window greedy merge of adjacent blocks
+  std::vector<Span> merged;
+  for (const Span &sp : spans) {
+    if (!merged.empty()) {
+      Span &last = merged.back();
+      std::vector<int32_t> t1, t2, tm;
+      bool d1, m1, d2, m2, dm, mm;
+      span_info(gates, last.a, last.b, &t1, &d1, &m1);
+      span_info(gates, sp.a, sp.b, &t2, &d2, &m2);
+      span_info(gates, last.a, sp.b, &tm, &dm, &mm);
+      const int cap = dm ? diag_max : k_max;
+      if (int(tm.size()) <= cap && gamma(tm, dm, mm) < gamma(t1, d1, m1) + gamma(t2, d2, m2)) {
+        last.b = sp.b;
+        continue;
+      }
+    }
+    merged.push_back(sp);
+  }
+  sv_plan *p = new sv_plan();
+  p->n = n;
+  for (const Span &sp : merged) {
+    std::vector<GateView> seg(gates.begin() + long(sp.a), gates.begin() + long(sp.b));
+    p->blocks.push_back(make_block(seg));
+  }
+  *out = p;
+  return SV_OK;
+}

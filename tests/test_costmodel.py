@@ -1,0 +1,133 @@
+"""Cost model and DP planner, host side (no GPU).
+
+* the host MLP forward equals the FP64 oracle forward on the same weights;
+* the windowed DP with the paper's score reaches the brute-force minimum over
+  every partition of a window into feasible consecutive blocks
+  (Eq. dp-recurrence);
+* DP plans (paper score and learned score) applied by the oracle equal the
+  unfused circuit;
+* the learned score fits held-out measured sweep times better than the
+  paper's gamma(k) = 4^k score scaled by least squares.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2608_16940_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def C(P):
+    from paper_2608_16940_amd import costmodel as C
+    return C
+
+
+def test_features(C):
+    f = C.features(30, [29, 3, 0], monomial=False)
+    np.testing.assert_allclose(f, [30 / 35, 3 / 8, 0, 3 / 35, 29 / 35, -0.25, -0.25, -0.25, -0.25, 0], rtol=1e-6)
+    g = C.features(12, [5, 6], monomial=True)
+    assert abs(g[9] - 0.75) < 1e-7
+
+
+def test_host_forward_matches_oracle(C):
+    p = C.init_params(3)
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((50, 10)).astype(np.float32)
+    y = C.forward_host(p, X)
+    ref, _ = oracle.mlp_forward([a.astype(np.float64) for a in C.split_params(p)], X.astype(np.float64))
+    np.testing.assert_allclose(y, ref, rtol=1e-9, atol=1e-9)
+
+
+def paper_score(block):
+    return 1 if block["diag"] else 4 ** block["k"]
+
+
+def brute_force_window(gates, k_max, diag_max):
+    h = len(gates)
+    best = math.inf
+    for cuts in itertools.product([0, 1], repeat=h - 1):
+        bounds = [0] + [i + 1 for i, c in enumerate(cuts) if c] + [h]
+        total = 0
+        ok = True
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            seg = gates[a:b]
+            k = len({q for g in seg for q in g.targets})
+            dg = all(g.diag for g in seg)
+            cap = diag_max if dg else k_max
+            if k > cap and b - a > 1:
+                ok = False
+                break
+            total += 1 if dg else 4 ** k
+        if ok:
+            best = min(best, total)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dp_paper_score_is_optimal(P, seed):
+    rng = np.random.default_rng(seed)
+    n = 5
+    gates = []
+    for _ in range(10):
+        r = rng.random()
+        if r < 0.4:
+            gates.append(W.Gate("su2", (int(rng.integers(n)),), W.haar_su2(rng)))
+        elif r < 0.7:
+            a, b = rng.choice(n, 2, replace=False)
+            gates.append(W.Gate("cz", (int(a), int(b)), W.cz(), diag=True))
+        else:
+            gates.append(W.random_dense(n, 2, rng))
+    for k_max, diag_max in [(2, 3), (3, 3), (4, 2)]:
+        plan = P.Plan.dp(n, gates, k_max=k_max, diag_max=diag_max, window=64)
+        got = sum(paper_score(b) for b in plan.blocks())
+        assert got == brute_force_window(gates, k_max, diag_max), (seed, k_max, diag_max)
+
+
+def test_dp_plans_equal_unfused_on_oracle(P, C):
+    n = 12
+    gates = W.headline(n, 5, seed=2)
+    ref = oracle.run(n, gates)
+    plans = [P.Plan.dp(n, gates, 5, 6, 64), P.Plan.dp(n, gates, 7, 7, 64, params=C.init_params(5)),
+             P.Plan.dp(n, gates, 4, 4, 16)]
+    for plan in plans:
+        psi = oracle.zero_state(n)
+        for b in plan.blocks():
+            assert b["k"] <= 7
+            oracle.apply_gate(psi, b["matrix"], b["targets"])
+        m = oracle.metrics(ref, psi)
+        assert m["infidelity"] < 1e-12 and m["max_abs"] < 1e-12
+        assert sum(b["n_gates"] for b in plan.blocks()) == len(gates)
+
+
+def test_learned_score_beats_paper_score_on_held_out_timings(C):
+    """Committed timing data: hold out every fifth row, fit, compare errors."""
+    path = os.path.join(os.path.dirname(C.WEIGHTS), "costmodel_data.csv")
+    if not os.path.exists(C.WEIGHTS) or not os.path.exists(path):
+        pytest.skip("no committed cost-model data")
+    rows = np.loadtxt(path, delimiter=",", skiprows=1)
+    X = rows[:, :10].astype(np.float32)
+    y = rows[:, 10]
+    params, meta = C.load()
+    test = np.arange(len(y)) % 5 == 0
+    # learned: the committed model was trained on the non-held-out rows only
+    assert meta.get("holdout") == "every fifth row"
+    err_mlp = np.sqrt(np.mean((C.forward_host(params, X[test]) - y[test]) ** 2))
+    # paper score: log t = a + b * log(4^k), plus a size term log 2^N, least squares on the training rows
+    k = np.rint(X[:, 1] * 8)
+    nq = np.rint(X[:, 0] * 35)
+    A = np.stack([np.ones_like(k), k * math.log(4), nq * math.log(2)], axis=1)
+    coef, *_ = np.linalg.lstsq(A[~test], y[~test], rcond=None)
+    err_paper = np.sqrt(np.mean((A[test] @ coef - y[test]) ** 2))
+    print("held-out RMSE log-time: learned %.3f, scaled 4^k score %.3f" % (err_mlp, err_paper))
+    assert err_mlp < err_paper

@@ -1,0 +1,121 @@
+"""Cost-model kernels on the GPU against the FP64 oracle, and the learned planner."""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2608_16940_amd import costmodel as C
+    return C
+
+
+def _data(B=300, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((B, 10)).astype(np.float32)
+    t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]).astype(np.float32)
+    return X, t
+
+
+def test_forward_backward_match_oracle(C):
+    import torch
+    X, t = _data()
+    p = C.init_params(7)
+    net = C.DeviceMLP(p, X.shape[0])
+    Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    y = net.forward(Xd).cpu().numpy()
+    P64 = [a.astype(np.float64) for a in C.split_params(p)]
+    yref, _ = oracle.mlp_forward(P64, X.astype(np.float64))
+    np.testing.assert_allclose(y, yref, rtol=1e-4, atol=1e-5)
+    g = net.backward(Xd, td).cpu().numpy()
+    loss_ref, gref = oracle.mlp_loss_grad(P64, X.astype(np.float64), t.astype(np.float64))
+    assert abs(net.loss.item() - loss_ref) <= 1e-4 * max(1.0, loss_ref)
+    gflat = np.concatenate([a.reshape(-1) for a in gref])
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3"], C.split_params(g), gref):
+        a = np.asarray(a, dtype=np.float64).reshape(-1)
+        b = b.reshape(-1)
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        assert rel <= 1e-3, (name, rel)
+    assert np.linalg.norm(g - gflat) / np.linalg.norm(gflat) <= 1e-3
+
+
+def test_adam_matches_oracle(C):
+    import torch
+    X, t = _data(64, 1)
+    p = C.init_params(2)
+    net = C.DeviceMLP(p, X.shape[0])
+    Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    P = [a.astype(np.float64) for a in C.split_params(p)]
+    m = [np.zeros_like(a) for a in P]
+    v = [np.zeros_like(a) for a in P]
+    for step in range(1, 4):
+        net.forward(Xd)
+        g = net.backward(Xd, td).cpu().numpy().astype(np.float64)
+        net.adam(lr=1e-2)
+        G = [np.asarray(a) for a in C.split_params(g)]
+        P, m, v = oracle.adam_step(P, G, m, v, t=step, lr=1e-2)
+        got = [np.asarray(a, dtype=np.float64) for a in C.split_params(net.params())]
+        for a, b in zip(got, P):
+            np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6)
+
+
+def test_training_reduces_loss(C):
+    X, t = _data(512, 3)
+    params, hist = C.train(X, t, steps=600, lr=3e-3, log_every=100)
+    print("loss", hist, flush=True)
+    assert hist[-1][1] < 0.1 * hist[0][1]
+
+
+def test_learned_plan_parity(C):
+    import paper_2608_16940_amd as P
+    params = C.load()[0] if os.path.exists(C.WEIGHTS) else C.init_params(0)
+    n = 18
+    gates = W.headline(n, 6, 1)
+    plan = P.Plan.dp(n, gates, k_max=7, diag_max=7, window=64, params=params)
+    sv = P.StateVector(n)
+    plan.run(sv)
+    got = oracle.decode(sv.physical_state(), sv.layout())
+    m = oracle.metrics(oracle.run(n, gates), got)
+    assert m["infidelity"] <= 1e-5 and m["max_abs"] <= 1e-5 and m["rel_l2"] <= 1e-5, m
+
+
+def test_learned_plan_not_slower_than_greedy(C):
+    """What the trained network gains: end-to-end execute time at N=27, learned DP vs greedy k<=5."""
+    import torch
+
+    import paper_2608_16940_amd as P
+    if not os.path.exists(C.WEIGHTS):
+        pytest.skip("no trained cost model committed")
+    params = C.load()[0]
+    n = 27
+    gates = W.brickwork(n, 12, 0)
+    plans = {"greedy": P.Plan.greedy(n, gates, 5),
+             "learned": P.Plan.dp(n, gates, k_max=7, diag_max=7, window=64, params=params)}
+    sv = P.StateVector(n)
+    res = {}
+    for name, plan in plans.items():
+        plan.run(sv)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            sv.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.run(sv)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        res[name] = (min(ts), len(plan))
+    print("greedy %.4f s (%d blocks), learned %.4f s (%d blocks), gain %.1f%%"
+          % (res["greedy"][0], res["greedy"][1], res["learned"][0], res["learned"][1],
+             100 * (1 - res["learned"][0] / res["greedy"][0])), flush=True)
+    assert res["learned"][0] <= 1.03 * res["greedy"][0]

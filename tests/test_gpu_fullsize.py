@@ -115,3 +115,27 @@ def test_echo_n30(P):
     s = sv.sample(99, 1000)
     assert np.all(s == 0)
     sv.close()
+
+
+@pytest.mark.parametrize("n", [33, 34])
+def test_largest_states_dispatch_limits(P, n):
+    """N=33/34: grids past 2^32 work-items are capped (shuffle, CDF block totals)."""
+    import torch
+    sv = P.StateVector(n)
+    H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2)
+    sv.apply(H, [0])          # shuffle lowering, bit 0
+    sv.apply(H, [5])          # shuffle lowering, bit 5
+    sv.apply(W.cnot(), [0, n - 1])
+    nrm = sv.norm()
+    assert abs(nrm - 1) < 1e-6
+    s = sv.sample(3, 4000)
+    bit0 = (s & 1).astype(np.int64)
+    top = ((s >> np.uint64(n - 1)) & np.uint64(1)).astype(np.int64)
+    assert np.all(bit0 == top)
+    assert np.all((s & ~np.uint64(1 | 32 | (1 << (n - 1)))) == 0)
+    assert 0.4 < bit0.mean() < 0.6 and 0.4 < ((s >> np.uint64(5)) & np.uint64(1)).astype(np.int64).mean() < 0.6
+    amps = gather(sv, np.array([0, 1 | (1 << (n - 1)), 32, 1]))
+    np.testing.assert_allclose(amps, [0.5, 0.5, 0.5, 0.0], atol=1e-6)
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
