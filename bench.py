@@ -93,6 +93,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one plain device copy of the state's size "
                          "(reference dispatch for scaling HBM byte counters)")
+    ap.add_argument("--workload", default="headline", choices=["headline", "learned", "batch", "precision"],
+                    help="headline (default): N=30 brickwork+QFT, greedy k<=5; learned: learned-DP vs greedy "
+                         "plans at N=34 depth 20; batch: 4096 small circuits in one launch; precision: k=6/7 "
+                         "FP32 vs BF16x3 sweeps at N=32")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -106,6 +110,13 @@ def main():
 
     import paper_2608_16940_amd as P
     import workloads as W
+
+    if args.workload == "learned":
+        return bench_learned(args)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "precision":
+        return bench_precision(args)
 
     n = args.n
     gates = W.headline(n, args.depth, args.seed)
@@ -209,6 +220,150 @@ def main():
         },
         "cpu_baseline": cpu,
         "stats_last_step": st,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def bench_learned(args):
+    """Learned-DP plan vs greedy plan on N=34 (128 GiB) depth-20 brickwork: plan + execute time, echo fidelity."""
+    import numpy as np
+    import torch
+
+    import paper_2608_16940_amd as P
+    import workloads as W
+    from paper_2608_16940_amd import costmodel as C
+
+    n = args.n if args.n != 30 else 34
+    depth = 20
+    gates = W.brickwork(n, depth, args.seed)
+    inv = W.inverse(gates)
+    params, meta = C.load()
+    sv = P.StateVector(n, device="cuda:0")
+    sync = torch.cuda.synchronize
+    # warm every lowering once on a few gates
+    P.Plan.greedy(n, gates[:200], 5).run(sv)
+    P.Plan.dp(n, gates[:200], 7, 7, 64, params=params).run(sv)
+    sync()
+    res = {}
+    for name in ("greedy", "learned"):
+        t0 = time.perf_counter()
+        if name == "greedy":
+            fwd = P.Plan.greedy(n, gates, args.kmax)
+            bwd = P.Plan.greedy(n, inv, args.kmax)
+        else:
+            fwd = P.Plan.dp(n, gates, 7, 7, 64, params=params)
+            bwd = P.Plan.dp(n, inv, 7, 7, 64, params=params)
+        plan_s = (time.perf_counter() - t0) / 2
+        sv.reset()
+        ex = _timed(lambda: fwd.run(sv), sync)
+        log("bench learned: %s %d blocks, execute %.3f s" % (name, len(fwd), ex))
+        bwd.run(sv)
+        sv.sync()
+        a0 = sv.amps[0].item()
+        echo = abs(a0) ** 2
+        ks = {}
+        for b in fwd.blocks():
+            ks[str(b["k"])] = ks.get(str(b["k"]), 0) + 1
+        res[name] = {"blocks": len(fwd), "blocks_by_k": ks, "plan_s": plan_s, "execute_s": ex,
+                     "end_to_end_s": plan_s + ex, "echo_fidelity": echo, "layout_identity":
+                     bool(np.array_equal(sv.layout(), np.arange(n)))}
+    sv.close()
+    g, l = res["greedy"], res["learned"]
+    out = {
+        "metric": "learned vs greedy fusion: end-to-end time (plan + execute), N=%d c64 depth %d" % (n, depth),
+        "value": g["end_to_end_s"] / l["end_to_end_s"], "unit": "x speedup (greedy time / learned time)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "N=%d complex64 brickwork depth %d (seed %d); greedy k<=%d vs learned-score DP "
+                               "(k<=7, window 64)" % (n, depth, args.seed, args.kmax), "gates": len(gates)},
+        "greedy": g, "learned": l,
+        "execute_gain": 1 - l["execute_s"] / g["execute_s"],
+        "cost_model": {k: meta.get(k) for k in ("rows", "rmse_log_ms_train", "rmse_log_ms_test", "n_values")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """4096 parametrised circuits (n ~ U[10,18], depth ~ U[8,32]) in one persistent launch."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as W
+    from paper_2608_16940_amd import batch as B
+
+    circs = W.batch_family(4096, seed=args.seed)
+    b = B.Batch(circs).allocate()
+    cfg, times = b.autotune(16)
+    sync = torch.cuda.synchronize
+    b.run(cfg)
+    ts = [_timed(lambda: b.run(cfg), sync) for _ in range(max(1, args.steps))]
+    t = min(ts)
+    updates = sum(len(g) * (1 << n) for n, g in circs)
+    # fidelity and <Z_0> against the oracle on a sample of circuits
+    z0 = b.run(cfg)
+    worst_f, worst_z = 0.0, 0.0
+    idx = list(range(0, 4096, 64))
+    for i in idx:
+        n, gates = circs[i]
+        ref = oracle.run(n, gates)
+        m = oracle.metrics(ref, b.state(i))
+        worst_f = max(worst_f, m["infidelity"])
+        worst_z = max(worst_z, abs(z0[i] - oracle.expect_z(ref, 0)))
+    out = {
+        "metric": "batched circuits/s (4096 circuits, one persistent launch)", "value": 4096 / t,
+        "unit": "circuits/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "4096 RY/RZ + CNOT-ladder circuits, n ~ U[10,18], depth ~ U[8,32], seed %d"
+                               % args.seed, "autotuned_pack_size": {str(n): int(cfg[n]) for n in range(10, 19)}},
+        "seconds": t, "amplitude_updates_per_s": updates / t,
+        "oracle_sample": {"circuits": len(idx), "max_infidelity": worst_f, "max_abs_dz0": worst_z},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args):
+    """k=6 and k=7 fused sweeps at N=32 (32 GiB): FP32 MFMA (Gauss) vs BF16x3 MFMA."""
+    import numpy as np
+    import torch
+
+    import paper_2608_16940_amd as P
+    import workloads as W
+
+    n = args.n if args.n != 30 else 32
+    sv = P.StateVector(n, device="cuda:0")
+    rng = np.random.default_rng(args.seed)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = {}
+    for k in (5, 6, 7):
+        g = W.random_dense(n, k, rng)
+        for prec in ("fp32", "bf16x3"):
+            sv.set_precision(prec)
+            sv.apply(g.matrix, g.targets)
+            ev0.record()
+            reps = 5
+            for _ in range(reps):
+                sv.apply(g.matrix, g.targets)
+            ev1.record()
+            ev1.synchronize()
+            ms = ev0.elapsed_time(ev1) / reps
+            sweep = 16.0 * (1 << n)
+            flops = 8.0 * (1 << k) * (1 << n)  # complex multiply-adds as 8 real flops
+            rows["k%d_%s" % (k, prec)] = {"ms": ms, "GBps": sweep / ms / 1e6, "TFLOPs": flops / ms / 1e9}
+            log("bench precision: k=%d %s %.3f ms" % (k, prec, ms))
+    sv.close()
+    out = {
+        "metric": "fused k-qubit sweep time at N=%d, FP32 MFMA vs BF16x3 MFMA" % n,
+        "value": rows["k7_bf16x3"]["GBps"], "unit": "GB/s (k=7, BF16x3)", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "fp32 / bf16x3 (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": "random dense k-qubit unitaries on random targets, N=%d complex64" % n},
+        "sweeps": rows,
     }
     print(json.dumps(out), flush=True)
 
