@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the learned-plan and BF16x3 legs reported after the timed region")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one plain device copy of the state's size "
                          "(reference dispatch for scaling HBM byte counters)")
@@ -173,6 +175,40 @@ def main():
     achieved = sweep_bytes / dom_avg / 1e9
     traffic = pmc_traffic()
     st = sv.stats()
+
+    def step_time(plan, reps, prec="fp32"):
+        sv.set_precision(prec)
+        sv.reset()
+        plan.run(sv)
+        sv.sample(0x5EED, args.shots)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sv.reset()
+            plan.run(sv)
+            sv.sample(0x5EED, args.shots)
+        torch.cuda.synchronize()
+        sv.set_precision("fp32")
+        return (time.perf_counter() - t0) / reps
+
+    extra = {}
+    if not args.no_extras:
+        from paper_2608_16940_amd import costmodel as C
+        params, _ = C.load()
+        lplan = P.Plan.learned(n, gates, params)
+        t_l = step_time(lplan, 3)
+        t_b = step_time(plan, 3, "bf16x3")
+        kl = {}
+        for b in lplan.blocks():
+            kl[str(b["k"])] = kl.get(str(b["k"]), 0) + 1
+        extra = {
+            "learned_plan": {"blocks": len(lplan), "blocks_by_k": kl, "ms_per_step": t_l * 1e3,
+                             "speedup_vs_greedy_step": (el / args.steps) / t_l},
+            "greedy_bf16x3": {"ms_per_step": t_b * 1e3, "gate_sweeps_per_s": nb / t_b,
+                              "speedup_vs_fp32_step": (el / args.steps) / t_b},
+        }
+        log("bench: learned plan %d blocks %.1f ms/step; greedy bf16x3 %.1f ms/step" % (len(lplan), t_l * 1e3,
+                                                                                       t_b * 1e3))
     if args.copy_probe:
         dst = torch.empty_like(sv.amps)
         dst.copy_(sv.amps)
@@ -220,6 +256,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "stats_last_step": st,
+        **extra,
     }
     print(json.dumps(out), flush=True)
 
@@ -250,7 +287,7 @@ def bench_learned(args):
     sync = torch.cuda.synchronize
     # warm every lowering once on a few gates
     P.Plan.greedy(n, gates[:200], 5).run(sv)
-    P.Plan.dp(n, gates[:200], 7, 7, 64, params=params).run(sv)
+    P.Plan.learned(n, gates[:200], params).run(sv)
     sync()
     res = {}
     for name in ("greedy", "learned"):
@@ -259,8 +296,8 @@ def bench_learned(args):
             fwd = P.Plan.greedy(n, gates, args.kmax)
             bwd = P.Plan.greedy(n, inv, args.kmax)
         else:
-            fwd = P.Plan.dp(n, gates, 7, 7, 64, params=params)
-            bwd = P.Plan.dp(n, inv, 7, 7, 64, params=params)
+            fwd = P.Plan.learned(n, gates, params)
+            bwd = P.Plan.learned(n, inv, params)
         plan_s = (time.perf_counter() - t0) / 2
         sv.reset()
         ex = _timed(lambda: fwd.run(sv), sync)
@@ -277,13 +314,27 @@ def bench_learned(args):
                      bool(np.array_equal(sv.layout(), np.arange(n)))}
     sv.close()
     g, l = res["greedy"], res["learned"]
+
+    def predicted(plan):
+        tot = 0.0
+        for b in plan.blocks():
+            f = C.features(n, list(b["targets"]), b["diag"])
+            tot += float(np.exp(C.forward_host(params, f[None])[0] + (n - 30) * np.log(2.0)))
+        return tot / 1e3
+
+    paper = P.Plan.dp(n, gates, 5, 5, 64, reorder=True)  # the method without the network: 4^k score
     out = {
         "metric": "learned vs greedy fusion: end-to-end time (plan + execute), N=%d c64 depth %d" % (n, depth),
         "value": g["end_to_end_s"] / l["end_to_end_s"], "unit": "x speedup (greedy time / learned time)",
         "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "N=%d complex64 brickwork depth %d (seed %d); greedy k<=%d vs learned-score DP "
-                               "(k<=7, window 64)" % (n, depth, args.seed, args.kmax), "gates": len(gates)},
+        "config": {"workload": "N=%d complex64 brickwork depth %d (seed %d); greedy k<=%d (circuit order) vs "
+                               "learned planner (commute-aware reorder + DP on predicted sweep times, cap chosen "
+                               "by the model among 4..7, window 64)" % (n, depth, args.seed, args.kmax),
+                   "gates": len(gates)},
         "greedy": g, "learned": l,
+        "predicted_s": {"greedy": predicted(P.Plan.greedy(n, gates, args.kmax)),
+                        "learned": predicted(P.Plan.learned(n, gates, params)),
+                        "paper_score_dp_with_reorder": predicted(paper), "paper_score_dp_blocks": len(paper)},
         "execute_gain": 1 - l["execute_s"] / g["execute_s"],
         "cost_model": {k: meta.get(k) for k in ("rows", "rmse_log_ms_train", "rmse_log_ms_test", "n_values")},
     }

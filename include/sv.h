@@ -169,11 +169,16 @@ const char *sv_last_error(void);
 #define SV_POLICY_FIRST_FREE 1 /* lowest-indexed eligible bit */
 #define SV_POLICY_LRU 2        /* least recently used qubit */
 
-/* Where the waves of a k <= 5 MFMA sweep keep the embedded gate operand:
- * in their own registers, or once per workgroup in LDS (default). */
+/* Where the waves of an MFMA sweep read the gate operand: their own
+ * registers (k <= 5), once per workgroup in LDS (k <= 6), or from global
+ * memory through the caches (k >= 5; always for k = 7).  AUTO (default)
+ * takes the placement measured fastest for each width and precision;
+ * kernels without the requested placement use their AUTO choice. */
 #define SV_OPT_MFMA_OPERAND 6
 #define SV_MFMA_OPERAND_REGS 0
 #define SV_MFMA_OPERAND_LDS 1
+#define SV_MFMA_OPERAND_GLOBAL 2
+#define SV_MFMA_OPERAND_AUTO 3
 
 int sv_set_option(sv_state *s, int key, int value);
 int sv_get_option(const sv_state *s, int key, int *value);

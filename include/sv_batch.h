@@ -59,11 +59,14 @@ int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, siz
                  void *stream);
 
 /*
- * Pick config[n] for every qubit count present in the batch by timing each
- * candidate pack size on a sample of up to `sample_per_size` circuits of that
- * size (hipEvent timing, one warm-up).  Writes SV_BATCH_CONFIG_LEN entries to
- * config_out and, if times_out is not NULL, the best time per circuit in
- * seconds per qubit count.  Uses states_dev / ws_dev like sv_batch_run.
+ * Pick config[n] for every qubit count present in the batch: a tuning subset
+ * of up to `sample_per_size` circuits of every size is run as one launch
+ * (hipEvent timing after one warm-up), starting from the default pack sizes,
+ * and each size's pack size is varied in turn over the powers of two that
+ * fit in LDS, keeping a change when the whole launch gets faster
+ * (coordinate descent).  Writes SV_BATCH_CONFIG_LEN entries to config_out
+ * and, if times_out is not NULL, the subset's launch time in seconds after
+ * each size was tuned.  Uses states_dev / ws_dev like sv_batch_run.
  */
 int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
                       const int64_t *state_offsets, int sample_per_size, int32_t *config_out, double *times_out,

@@ -44,18 +44,29 @@ int sv_plan_greedy(int n_qubits, int n_gates, const int32_t *ks, const int32_t *
  * diag_max for all-diagonal blocks) and always i-1 (an over-cap gate stays a
  * singleton).  Backtracking gives the boundaries; a greedy pass then merges
  * adjacent blocks across window boundaries when the merged block is within
- * the cap and scores lower than the two apart.  No reordering.
+ * the cap and scores lower than the two apart.  Gates keep circuit order
+ * unless SV_PLAN_REORDER is set.
  *   score = SV_SCORE_PAPER:   Gamma = 4^k (dense), 1 (diagonal)
- *   score = SV_SCORE_LEARNED: Gamma = exp(MLP(features)), the cost model's
- *           predicted sweep time (sv_mlp.h), params host FP32 (nin, hid).
+ *   score = SV_SCORE_LEARNED: Gamma = exp(MLP(features) + (N - 30) ln 2), the
+ *           cost model's predicted sweep time in ms (the network predicts it
+ *           at N=30 scale; sv_mlp.h), params host FP32 (nin, hid).
  * Physical positions for the features are the logical qubits (identity
  * layout at planning time).
  */
 #define SV_SCORE_PAPER 0
 #define SV_SCORE_LEARNED 1
+/* flags: SV_PLAN_REORDER first applies a commute-aware reorder (Section
+ * IV-C): a gate moves only across gates on disjoint qubits, so each qubit's
+ * gate sequence is kept; clusters are grown from the dependency front,
+ * taking at each step the ready gate that enlarges the cluster's qubit set
+ * least (earliest on ties) while it stays within max(k_max, diag_max). */
+#define SV_PLAN_REORDER 1
+/* flags: SV_PLAN_SEARCH_CAP (learned score only) plans with every width cap
+ * from 4 to k_max and keeps the plan of least predicted total time. */
+#define SV_PLAN_SEARCH_CAP 2
 int sv_plan_dp(int n_qubits, int n_gates, const int32_t *ks, const int32_t *targets, const double *mats,
                const int8_t *diag, int k_max, int diag_max, int window, int score, const float *mlp_params_host,
-               int mlp_nin, int mlp_hid, sv_plan **out);
+               int mlp_nin, int mlp_hid, int flags, sv_plan **out);
 
 /*
  * Cost-model features of one fused sweep (SV_MLP_FEATURES floats): N/35,

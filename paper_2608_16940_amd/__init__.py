@@ -202,8 +202,10 @@ class Plan:
 
     @classmethod
     def dp(cls, n: int, gates, k_max: int = 5, diag_max: int = 6, window: int = 64, params=None,
-           nin: int = 10, hid: int = 64) -> "Plan":
-        """Windowed DP fusion: paper score (params None) or learned sweep-time score (MLP params)."""
+           nin: int = 10, hid: int = 64, reorder: bool = False, search_cap: bool = False) -> "Plan":
+        """Windowed DP fusion: paper score (params None) or learned sweep-time score (MLP params);
+        reorder=True first applies the commute-aware reorder; search_cap=True lets the learned
+        score pick the width cap (4..k_max)."""
         ks, tg, mats, dg = cls._flat(gates)
         h = ctypes.c_void_p()
         if params is None:
@@ -215,8 +217,15 @@ class Plan:
         check(lib().sv_plan_dp(int(n), len(gates), ks.ctypes.data_as(_native._i32p),
                                tg.ctypes.data_as(_native._i32p), mats.ctypes.data_as(_native._dp),
                                dg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), int(k_max), int(diag_max),
-                               int(window), score, pp, int(nin), int(hid), ctypes.byref(h)))
+                               int(window), score, pp, int(nin), int(hid),
+                               (1 if reorder else 0) | (2 if search_cap else 0), ctypes.byref(h)))
         return cls(h, int(n))
+
+    @classmethod
+    def learned(cls, n: int, gates, params, k_max: int = 7, window: int = 64) -> "Plan":
+        """The learned planner: commute-aware reorder + DP on predicted sweep times, cap chosen by the model."""
+        return cls.dp(n, gates, k_max=k_max, diag_max=k_max, window=window, params=params, reorder=True,
+                      search_cap=True)
 
     def __len__(self) -> int:
         v = ctypes.c_int()

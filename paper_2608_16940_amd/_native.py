@@ -26,7 +26,7 @@ OPT_LOW_BITS = 5
 OPT_MFMA_OPERAND = 6
 OPT_POLICY = 7
 POLICY = {"belady": 0, "first_free": 1, "lru": 2}
-MFMA_OPERAND = {"regs": 0, "lds": 1}
+MFMA_OPERAND = {"regs": 0, "lds": 1, "global": 2, "auto": 3}
 
 VARIANT = {"auto": 0, "valu": 1, "shuffle": 2, "mfma": 3, "generic": 4}
 PRECISION = {"fp32": 0, "bf16x3": 1}
@@ -97,7 +97,8 @@ SIGNATURES = [
                                            ctypes.POINTER(ctypes.c_float), ctypes.c_int, _dp]),
     ("sv_plan_dp", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, _dp, ctypes.POINTER(ctypes.c_int8),
                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                  ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+                                  ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(_vp)]),
     ("sv_cost_features", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_float)]),
     ("sv_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(sv_batch_circuit)]),

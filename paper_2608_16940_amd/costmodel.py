@@ -1,7 +1,10 @@
 """Learned sweep-time cost model (argument marshalling and driver loops only).
 
 The network, its training kernels and the planner that uses it live in
-libsv (``sv_mlp.h``, ``sv_plan.h``).  This module gathers training data by
+libsv (``sv_mlp.h``, ``sv_plan.h``).  The network predicts the log run
+time in ms of one sweep scaled to N=30, log(ms) - (N - 30) ln 2: a sweep's
+time grows as 2^N once the state leaves the caches, so the model learns the
+relative costs of widths and target patterns and extrapolates in N.  This module gathers training data by
 timing the library's own fused sweeps on the GPU, trains the network with
 the library's HIP forward / backward / Adam kernels, and stores or loads the
 trained parameters.
@@ -146,8 +149,11 @@ def train(X: np.ndarray, y: np.ndarray, steps: int = 3000, lr: float = 3e-3, see
 def _random_block(rng, n, k, kind):
     """A k-qubit operator of the given structural kind on random targets."""
     import workloads as W
-    pat = rng.integers(0, 4)
-    if pat == 0:
+    pat = rng.integers(0, 5)
+    if pat == 4:
+        w0 = int(rng.integers(0, n - (k + 3) + 1)) if n >= k + 3 else 0
+        t = w0 + rng.choice(min(k + 3, n), size=k, replace=False)
+    elif pat == 0:
         t = rng.choice(n, size=k, replace=False)
     elif pat == 1:
         s0 = int(rng.integers(0, n - k + 1))
@@ -201,7 +207,7 @@ def collect(n_values, samples_per_n, seed: int = 0, reps: int = 3, device="cuda:
             L = sv.layout()
             phys = [int(L[q]) for q in t]
             Xs.append(features(int(n), phys, mono))
-            ys.append(math.log(ms))
+            ys.append(math.log(ms) - (int(n) - 30) * math.log(2.0))
             rows.append((int(n), k, phys, kind, ms))
         if log:
             log("collect n=%d samples=%d %.1f s" % (n, cnt, time.perf_counter() - t0))
@@ -227,7 +233,7 @@ def load(path=WEIGHTS):
 # ------------------------------------------------------------------ command line
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "costmodel_data.csv")
 FIT_N = [24, 25, 26, 27, 28, 29, 30, 31, 32, 33]
-FIT_SAMPLES = [300, 300, 300, 300, 250, 200, 160, 120, 80, 50]
+FIT_SAMPLES = [250, 250, 250, 300, 300, 250, 220, 160, 100, 60]
 
 
 def fit(seed: int = 0, steps: int = 4000, log=print):
@@ -245,7 +251,7 @@ def fit(seed: int = 0, steps: int = 4000, log=print):
             "loss_history": hist}
     save(params, meta=meta)
     with open(DATA, "w") as f:
-        f.write(",".join(["f%d" % i for i in range(NIN)] + ["log_ms", "n", "k", "kind"]) + "\n")
+        f.write(",".join(["f%d" % i for i in range(NIN)] + ["log_ms_at_n30", "n", "k", "kind"]) + "\n")
         for xi, yi, r in zip(X, y, rows):
             f.write(",".join("%.7g" % v for v in xi) + ",%.7g,%d,%d,%d\n" % (yi, r[0], r[1],
                                                                         {"dense": 0, "diag": 1, "perm": 2}[r[3]]))

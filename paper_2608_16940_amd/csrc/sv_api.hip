@@ -67,7 +67,7 @@ struct sv_state {
   int lazy = 0;
   int low_bits = 12;
   int policy = SV_POLICY_BELADY;
-  int opsrc = SV_MFMA_OPERAND_LDS;
+  int opsrc = SV_MFMA_OPERAND_AUTO;
   // relabel policy state: planner hints and recency per logical qubit
   bool have_hints = false;
   int64_t next_use[64];
@@ -689,7 +689,7 @@ int sv_set_option(sv_state *s, int key, int value) {
       s->policy = value;
       return SV_OK;
     case SV_OPT_MFMA_OPERAND:
-      if (value != SV_MFMA_OPERAND_REGS && value != SV_MFMA_OPERAND_LDS) break;
+      if (value < SV_MFMA_OPERAND_REGS || value > SV_MFMA_OPERAND_AUTO) break;
       s->opsrc = value;
       return SV_OK;
     default:

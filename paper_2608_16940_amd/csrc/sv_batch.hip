@@ -367,43 +367,55 @@ int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev
     set_error("bad autotune argument");
     return SV_ERR_ARG;
   }
+  // tuning subset: up to sample_per_size circuits of every size, run together
+  // so that the measured time is the throughput of a full launch
+  std::vector<sv_batch_circuit> sample;
+  std::vector<int64_t> offs;
+  int per_size[SV_BATCH_CONFIG_LEN] = {0};
+  for (int i = 0; i < count; ++i) {
+    const int n = circs[i].n_qubits;
+    if (n < 1 || n > SV_BATCH_MAX_QUBITS || per_size[n] >= sample_per_size) continue;
+    ++per_size[n];
+    sample.push_back(circs[i]);
+    offs.push_back(state_offsets[i]);
+  }
   int32_t cfg[SV_BATCH_CONFIG_LEN];
   default_config(cfg);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<double> z(std::max<size_t>(1, sample.size()));
+  auto measure = [&](const int32_t *c, double *t_out) -> int {
+    Packed pk;
+    int rc = pack_batch(int(sample.size()), sample.data(), states_bytes, offs.data(), c, &pk);
+    if (rc) return rc;
+    float ms = 0.f;
+    rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);  // warm-up
+    if (rc) return rc;
+    rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);
+    if (rc) return rc;
+    *t_out = double(ms) * 1e-3;
+    return SV_OK;
+  };
+  double best_t = 0;
+  int rc = measure(cfg, &best_t);
+  if (rc) return rc;
   if (times_out)
     for (int n = 0; n < SV_BATCH_CONFIG_LEN; ++n) times_out[n] = 0.0;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  // coordinate descent over the pack size of every size present
   for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
-    std::vector<sv_batch_circuit> sample;
-    std::vector<int64_t> offs;
-    for (int i = 0; i < count && int(sample.size()) < sample_per_size; ++i)
-      if (circs[i].n_qubits == n) {
-        sample.push_back(circs[i]);
-        offs.push_back(state_offsets[i]);
-      }
-    if (sample.empty()) continue;
-    std::vector<double> z(sample.size());
-    double best_t = 1e300;
-    int best_p = 1;
+    if (per_size[n] == 0) continue;
     for (int P = 1; P <= kMaxPack; P *= 2) {
-      if (P > 1 && (int64_t(P) << n) > kLdsAmps) break;
+      if (P == cfg[n] || (P > 1 && (int64_t(P) << n) > kLdsAmps)) continue;
       int32_t trial[SV_BATCH_CONFIG_LEN];
       std::memcpy(trial, cfg, sizeof(trial));
       trial[n] = P;
-      Packed pk;
-      int rc = pack_batch(int(sample.size()), sample.data(), states_bytes, offs.data(), trial, &pk);
+      double t = 0;
+      rc = measure(trial, &t);
       if (rc) return rc;
-      float ms = 0.f;
-      rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);  // warm-up
-      if (rc) return rc;
-      rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);
-      if (rc) return rc;
-      const double t = double(ms) * 1e-3 / double(sample.size());
       if (t < best_t) {
         best_t = t;
-        best_p = P;
+        cfg[n] = P;
       }
     }
-    cfg[n] = best_p;
     if (times_out) times_out[n] = best_t;
   }
   std::memcpy(config_out, cfg, sizeof(cfg));

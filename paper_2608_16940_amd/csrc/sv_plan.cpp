@@ -279,7 +279,8 @@ struct Scorer {
     sv_cost_features(n, k, tuple_sorted.data(), all_mono ? 1 : 0, f);
     double y = 0;
     sv_mlp_forward_host(params, nin, hid, f, 1, &y);
-    const double g = std::exp(y);
+    // the model predicts log(ms) at N = 30 scale; a sweep's time grows as 2^N
+    const double g = std::exp(y + (n - 30) * std::log(2.0));
     cache.emplace(std::move(key), g);
     return g;
   }
@@ -303,11 +304,76 @@ void span_info(const std::vector<GateView> &gates, size_t a, size_t b, std::vect
   std::sort(tuple->begin(), tuple->end());
 }
 
+// Commute-aware reorder (Section IV-C: a gate moves only across neighbours it
+// commutes with; here, gates on disjoint qubits).  Any order that keeps each
+// qubit's gate sequence is equivalent.  Clusters are grown from the dependency
+// front: start with the earliest ready gate, then repeatedly take the ready
+// gate whose qubits enlarge the cluster's set least (earliest on ties) while
+// the set stays within `cap`; emit the cluster's gates consecutively.
+std::vector<size_t> commute_order(const std::vector<GateView> &gates, int n, int cap) {
+  const size_t G = gates.size();
+  std::vector<std::vector<size_t>> per_q(static_cast<size_t>(n));
+  for (size_t g = 0; g < G; ++g)
+    for (int j = 0; j < gates[g].k; ++j) per_q[size_t(gates[g].t[j])].push_back(g);
+  std::vector<size_t> head(size_t(n), 0);
+  std::vector<bool> done(G, false);
+  auto ready = [&](size_t g) {
+    for (int j = 0; j < gates[g].k; ++j) {
+      const size_t q = size_t(gates[g].t[j]);
+      if (head[q] >= per_q[q].size() || per_q[q][head[q]] != g) return false;
+    }
+    return true;
+  };
+  auto take = [&](size_t g, std::vector<size_t> &out) {
+    done[g] = true;
+    out.push_back(g);
+    for (int j = 0; j < gates[g].k; ++j) ++head[size_t(gates[g].t[j])];
+  };
+  std::vector<size_t> order;
+  order.reserve(G);
+  size_t first = 0;
+  while (order.size() < G) {
+    while (done[first]) ++first;
+    // the earliest unscheduled gate is always ready: its predecessors are earlier
+    std::vector<int32_t> set(gates[first].t, gates[first].t + gates[first].k);
+    take(first, order);
+    while (true) {
+      size_t best = G;
+      int best_w = 1 << 30;
+      // candidates: the head gate of every qubit (ready gates are heads of all their qubits)
+      for (int q = 0; q < n; ++q) {
+        if (head[size_t(q)] >= per_q[size_t(q)].size()) continue;
+        const size_t g = per_q[size_t(q)][head[size_t(q)]];
+        if (done[g] || !ready(g)) continue;
+        int w = int(set.size());
+        for (int j = 0; j < gates[g].k; ++j)
+          if (std::find(set.begin(), set.end(), gates[g].t[j]) == set.end()) ++w;
+        if (w > cap && gates[g].k <= cap) continue;
+        if (w > cap) continue;
+        if (w < best_w || (w == best_w && g < best)) {
+          best_w = w;
+          best = g;
+        }
+      }
+      if (best == G) break;
+      for (int j = 0; j < gates[best].k; ++j)
+        if (std::find(set.begin(), set.end(), gates[best].t[j]) == set.end()) set.push_back(gates[best].t[j]);
+      take(best, order);
+    }
+  }
+  return order;
+}
+
 }  // namespace
+
+namespace {
+sv_plan *plan_dp_once(int n, const std::vector<GateView> &input, int k_max, int diag_max, int window, int score,
+                      const float *mlp_params, int mlp_nin, int mlp_hid, int flags, double *predicted);
+}
 
 extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
                           const int8_t *diag, int k_max, int diag_max, int window, int score,
-                          const float *mlp_params, int mlp_nin, int mlp_hid, sv_plan **out) {
+                          const float *mlp_params, int mlp_nin, int mlp_hid, int flags, sv_plan **out) {
   if (!out || ngates < 0 || (ngates > 0 && (!ks || !targets || !mats)) || k_max < 1 || k_max > 8 ||
       diag_max < 1 || diag_max > 8 || window < 1 || n < SV_MIN_QUBITS || n > SV_MAX_QUBITS ||
       (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED) ||
@@ -319,6 +385,42 @@ extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *t
   if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
     sv::set_error("bad gate in list");
     return SV_ERR_ARG;
+  }
+  if ((flags & SV_PLAN_SEARCH_CAP) && score == SV_SCORE_LEARNED) {
+    // the cost model also picks the width cap: plan with every cap up to
+    // k_max and keep the plan with the lowest predicted total time
+    sv_plan *best = nullptr;
+    double best_t = 1e300;
+    for (int cap = std::min(4, k_max); cap <= k_max; ++cap) {
+      double t = 0;
+      sv_plan *p = plan_dp_once(n, gates, cap, std::min(cap, diag_max), window, score, mlp_params, mlp_nin, mlp_hid,
+                                flags, &t);
+      if (t < best_t) {
+        delete best;
+        best = p;
+        best_t = t;
+      } else {
+        delete p;
+      }
+    }
+    *out = best;
+    return SV_OK;
+  }
+  double t = 0;
+  *out = plan_dp_once(n, gates, k_max, diag_max, window, score, mlp_params, mlp_nin, mlp_hid, flags, &t);
+  return SV_OK;
+}
+
+namespace {
+sv_plan *plan_dp_once(int n, const std::vector<GateView> &input, int k_max, int diag_max, int window, int score,
+                      const float *mlp_params, int mlp_nin, int mlp_hid, int flags, double *predicted) {
+  std::vector<GateView> gates(input);
+  if (flags & SV_PLAN_REORDER) {
+    const std::vector<size_t> order = commute_order(gates, n, std::max(k_max, diag_max));
+    std::vector<GateView> re;
+    re.reserve(gates.size());
+    for (size_t g : order) re.push_back(gates[g]);
+    gates.swap(re);
   }
   Scorer gamma{score, n, mlp_params, mlp_nin, mlp_hid, {}};
   const int cap_any = std::max(k_max, diag_max);
@@ -380,10 +482,16 @@ extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *t
   }
   sv_plan *p = new sv_plan();
   p->n = n;
+  double total = 0;
   for (const Span &sp : merged) {
     std::vector<GateView> seg(gates.begin() + long(sp.a), gates.begin() + long(sp.b));
+    std::vector<int32_t> tp;
+    bool dg, mo;
+    span_info(gates, sp.a, sp.b, &tp, &dg, &mo);
+    total += gamma(tp, dg, mo);
     p->blocks.push_back(make_block(seg));
   }
-  *out = p;
-  return SV_OK;
+  *predicted = total;
+  return p;
 }
+}  // namespace

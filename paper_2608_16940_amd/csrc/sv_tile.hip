@@ -103,23 +103,29 @@ struct Scheme {
   static constexpr int bytes = (alg == ALG_GAUSS_F32) ? 3 * (1 << (2 * K + 2)) : (1 << (2 * K + 4));
 };
 
+// Occupancy target per gate width (waves per SIMD the register budget is cut for).
+template <int K>
+struct WavesPerSimd {
+  static constexpr int value = K <= 4 ? 4 : (K == 5 ? 3 : 2);
+};
+
 template <int K, int M, int PREC, int OPS>
-__global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
-  constexpr int WAVES = 1 << (M - 5);
-  constexpr int NT = 64 * WAVES;
+__global__ __launch_bounds__(256, WavesPerSimd<K>::value) void k_tile_mfma(TileArgs a) {
+  constexpr int NT = 256;               // four waves for every gate width
   constexpr int S = K + M;
   constexpr int TILE = 1 << S;
-  constexpr int CHUNKS = 1 << (K - 2);  // 16-byte chunks per thread per tile
-  constexpr int AH = 1 << (K - 1);      // amplitudes per lane half
+  constexpr int CHUNKS = TILE / 2 / NT;  // 16-byte chunks per thread per tile
+  constexpr int AH = 1 << (K - 1);       // amplitudes per lane half
   constexpr int ALG = Scheme<K, PREC>::alg;
   constexpr int NOPF = Scheme<K, PREC>::bytes / 4;  // operand size in floats
-  // embedding: 2^(K+1) real outputs in 32-row tiles, 2^K reals per lane half
-  constexpr int EMT = (2 << K) / 32;
-  constexpr int HALF = 1 << K;
+  constexpr int HALF = 1 << K;           // embedding: reals per lane half
   constexpr int KQ = HALF / 4;
-  // Gauss: 2^K complex outputs in 32-row tiles, AH amplitudes per lane half
-  constexpr int GMT = (1 << K) / 32;
-  constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * GMT : EMT;
+  constexpr int MTT = (ALG == ALG_GAUSS_F32) ? (1 << K) / 32 : (2 << K) / 32;  // 32-row output tiles
+  constexpr int NCB = (1 << M) / 32;     // 32-group column blocks per tile
+  static_assert(MTT * NCB >= 4 && (MTT * NCB) % 4 == 0, "four waves share the (block, tile) pairs");
+  constexpr int MPW = MTT * NCB / 4;     // output tiles per wave
+  constexpr bool SHARED_GROUPS = NCB < 4;  // several waves work on the same groups
+  constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * MPW : MPW;
   __shared__ float2 lds[TILE];
   __shared__ float opl_s[OPS == OP_LDS ? NOPF : 1];
 
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
   int64_t goff_t = 0;
   int lam_t = 0, lamo_t = 0;
 #pragma unroll
-  for (int b = 1; b <= M + 1; ++b) {
+  for (int b = 1; b <= 8; ++b) {
     if ((t >> (b - 1)) & 1) {
       goff_t |= int64_t(1) << a.sbit[b];
       lam_t |= 1 << a.loc_in[b];
@@ -138,6 +144,11 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
     }
   }
   const int bin = 1 << a.lb_in, bout = 1 << a.lb_out;
+
+  // wave -> column block and its output tiles mt0 + j * (4 / NCB)
+  const int cb = wave % NCB;
+  const int mt0 = wave / NCB;
+  constexpr int MT_STEP = 4 / NCB;
 
   // ---- operand
   const float *opf = reinterpret_cast<const float *>(a.op);
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
       return opsrc[i * 64 + lane];
   };
 
-  const int g = 32 * wave + (lane & 31);
+  const int g = 32 * cb + (lane & 31);
   const int h = lane >> 5;
   const int gbase = g << K;
 
@@ -183,9 +194,6 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
     }
     __syncthreads();
 
-    // Each wave reads and then overwrites only its own 32 groups; LDS
-    // operations of one wave complete in order, so no barrier is needed
-    // between its reads and its writes.
     floatx16 acc[NACC];
 #pragma unroll
     for (int m = 0; m < NACC; ++m)
@@ -200,22 +208,25 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
         const float2 x = lds[swz<K>(gbase | (h * AH + kk))];
         const float xs = x.x + x.y;
 #pragma unroll
-        for (int mt = 0; mt < GMT; ++mt) {
-          const int i0 = (0 * GMT + mt) * AH + kk;
-          const int i1 = (1 * GMT + mt) * AH + kk;
-          const int i2 = (2 * GMT + mt) * AH + kk;
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(i0), x.x, acc[mt], 0, 0, 0);
-          acc[GMT + mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(i1), x.y, acc[GMT + mt], 0, 0, 0);
-          acc[2 * GMT + mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(i2), xs, acc[2 * GMT + mt], 0, 0, 0);
+        for (int j = 0; j < MPW; ++j) {
+          const int mt = mt0 + j * MT_STEP;
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv((0 * MTT + mt) * AH + kk), x.x, acc[j], 0, 0, 0);
+          acc[MPW + j] =
+              __builtin_amdgcn_mfma_f32_32x32x2f32(opv((1 * MTT + mt) * AH + kk), x.y, acc[MPW + j], 0, 0, 0);
+          acc[2 * MPW + j] =
+              __builtin_amdgcn_mfma_f32_32x32x2f32(opv((2 * MTT + mt) * AH + kk), xs, acc[2 * MPW + j], 0, 0, 0);
         }
       }
+      if constexpr (SHARED_GROUPS) __syncthreads();  // sibling waves finished reading these groups
 #pragma unroll
-      for (int mt = 0; mt < GMT; ++mt)
+      for (int j = 0; j < MPW; ++j) {
+        const int mt = mt0 + j * MT_STEP;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const float t1 = acc[mt][r], t2 = acc[GMT + mt][r], t3 = acc[2 * GMT + mt][r];
+          const float t1 = acc[j][r], t2 = acc[MPW + j][r], t3 = acc[2 * MPW + j][r];
           lds[swz<K>(gbase | (h * AH + 16 * mt + r))] = make_float2(t1 - t2, t3 - t1 - t2);
         }
+      }
     } else if constexpr (ALG == ALG_EMBED_F32) {
       // step kk uses real (HALF h + kk) of this lane's group
 #pragma unroll
@@ -223,14 +234,19 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
         const float2 x = lds[swz<K>(gbase | (h * AH + (kk >> 1)))];
         const float xv = (kk & 1) ? x.y : x.x;
 #pragma unroll
-        for (int mt = 0; mt < EMT; ++mt)
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(mt * HALF + kk), xv, acc[mt], 0, 0, 0);
+        for (int j = 0; j < MPW; ++j) {
+          const int mt = mt0 + j * MT_STEP;
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv(mt * HALF + kk), xv, acc[j], 0, 0, 0);
+        }
       }
+      if constexpr (SHARED_GROUPS) __syncthreads();
 #pragma unroll
-      for (int mt = 0; mt < EMT; ++mt)
+      for (int j = 0; j < MPW; ++j) {
+        const int mt = mt0 + j * MT_STEP;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[mt][2 * e], acc[mt][2 * e + 1]);
+          lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[j][2 * e], acc[j][2 * e + 1]);
+      }
     } else {
       const shortx4 *oph = reinterpret_cast<const shortx4 *>(opsrc);
       constexpr int UNR = (K <= 5) ? KQ : 4;
@@ -249,26 +265,30 @@ __global__ __launch_bounds__(64 << (M - 5)) void k_tile_mfma(TileArgs a) {
           bl[e] = short(lo);
         }
 #pragma unroll
-        for (int mt = 0; mt < EMT; ++mt) {
+        for (int j = 0; j < MPW; ++j) {
+          const int mt = mt0 + j * MT_STEP;
           shortx4 ah, al;
           if constexpr (OPS == OP_REG) {
-            const int ih = 2 * (mt * KQ + kk), il = 2 * (EMT * KQ + mt * KQ + kk);
+            const int ih = 2 * (mt * KQ + kk), il = 2 * (MTT * KQ + mt * KQ + kk);
             ah = __builtin_bit_cast(shortx4, make_float2(ra[ih], ra[ih + 1]));
             al = __builtin_bit_cast(shortx4, make_float2(ra[il], ra[il + 1]));
           } else {
             ah = oph[(mt * KQ + kk) * 64 + lane];
-            al = oph[(EMT * KQ + mt * KQ + kk) * 64 + lane];
+            al = oph[(MTT * KQ + mt * KQ + kk) * 64 + lane];
           }
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[mt], 0, 0, 0);
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[mt], 0, 0, 0);
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[mt], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[j], 0, 0, 0);
         }
       }
+      if constexpr (SHARED_GROUPS) __syncthreads();
 #pragma unroll
-      for (int mt = 0; mt < EMT; ++mt)
+      for (int j = 0; j < MPW; ++j) {
+        const int mt = mt0 + j * MT_STEP;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[mt][2 * e], acc[mt][2 * e + 1]);
+          lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[j][2 * e], acc[j][2 * e + 1]);
+      }
     }
     __syncthreads();
 
@@ -362,8 +382,8 @@ unsigned grid_of(int64_t ntiles) { return unsigned(ntiles > 0x7fffffff ? 0x7ffff
 
 template <int K, int M, int PREC, int OPS>
 hipError_t tile_mfma_k(const TilePlan &tp, float2 *psi, const void *op, hipStream_t st) {
-  constexpr int NT = 64 << (M - 5);
-  constexpr int CHUNKS = 1 << (K - 2);
+  constexpr int NT = 256;
+  constexpr int CHUNKS = (1 << (K + M)) / 2 / NT;
   TileArgs a;
   fill_args(tp, NT, CHUNKS, psi, op, &a);
   hipLaunchKernelGGL((k_tile_mfma<K, M, PREC, OPS>), dim3(grid_of(a.ntiles)), dim3(NT), 0, st, a);
@@ -498,15 +518,20 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out) {
 
 hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi, const void *op, hipStream_t st) {
   const bool bf = (prec == SV_PREC_BF16X3);
-  const bool regs = (opsrc == SV_MFMA_OPERAND_REGS);
+  int o = opsrc;
+  if (o == SV_MFMA_OPERAND_AUTO)  // measured at N=30 on MI355X: LDS up to k=5 and FP32 k=6, caches beyond
+    o = (tp.K <= 5 || (tp.K == 6 && !bf)) ? SV_MFMA_OPERAND_LDS : SV_MFMA_OPERAND_GLOBAL;
   switch (tp.K) {
     case 4:
-      if (regs) return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
+      if (o == SV_MFMA_OPERAND_REGS) return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
       return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
     case 5:
-      if (regs) return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
+      if (o == SV_MFMA_OPERAND_REGS) return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
+      if (o == SV_MFMA_OPERAND_GLOBAL) return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
       return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
-    case 6: return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+    case 6:
+      if (o == SV_MFMA_OPERAND_LDS) return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+      return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
     case 7: return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
     default: return hipErrorInvalidValue;
   }

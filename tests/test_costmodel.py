@@ -131,3 +131,35 @@ def test_learned_score_beats_paper_score_on_held_out_timings(C):
     err_paper = np.sqrt(np.mean((A[test] @ coef - y[test]) ** 2))
     print("held-out RMSE log-time: learned %.3f, scaled 4^k score %.3f" % (err_mlp, err_paper))
     assert err_mlp < err_paper
+
+
+def test_reordered_plans_keep_each_qubits_gate_order(P, C):
+    """The commute-aware reorder moves gates only across gates on disjoint qubits."""
+    n = 10
+    gates = W.brickwork(n, 4, 7) + W.qft(n)
+    ref = oracle.run(n, gates)
+    for plan in [P.Plan.dp(n, gates, 5, 5, 64, reorder=True),
+                 P.Plan.learned(n, gates, C.init_params(4)),
+                 P.Plan.dp(n, gates, 3, 3, 8, reorder=True)]:
+        psi = oracle.zero_state(n)
+        for b in plan.blocks():
+            oracle.apply_gate(psi, b["matrix"], b["targets"])
+        m = oracle.metrics(ref, psi)
+        assert m["infidelity"] < 1e-12 and m["max_abs"] < 1e-12
+        assert sum(b["n_gates"] for b in plan.blocks()) == len(gates)
+
+
+def test_learned_planner_search_prefers_cheaper_plan(P, C):
+    if not os.path.exists(C.WEIGHTS):
+        pytest.skip("no committed cost model")
+    params, _ = C.load()
+    n = 30
+    gates = W.brickwork(n, 8, 0)
+
+    def predicted(plan):
+        return sum(float(np.exp(C.forward_host(params, C.features(n, list(b["targets"]), b["diag"])[None])[0]))
+                   for b in plan.blocks())
+    best = predicted(P.Plan.learned(n, gates, params))
+    for cap in (4, 5, 6, 7):
+        assert best <= predicted(P.Plan.dp(n, gates, cap, cap, 64, params=params, reorder=True)) + 1e-9
+    assert best < predicted(P.Plan.greedy(n, gates, 5))

@@ -1,0 +1,105 @@
+"""Wide fused sweeps (k=6, 7) in FP32 and BF16x3 at N=28 against the oracle.
+
+Brickwork depth 16 (seed 0) fused greedily with caps 6 and 7, and by the
+learned planner, run on the GPU in each MFMA precision; the result is compared
+at 2050 seeded indices with complex128 oracle amplitudes stored by
+tests/golden/make_brickwork_n28_golden.py, and the whole-state fidelity is
+checked by an echo (fused circuit, then the fused inverse, back to |0...0>).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N = 28
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "brickwork_n28_amplitudes.txt")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2608_16940_amd as P
+    P.lib()
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def read_golden():
+    idx, vals = [], []
+    with open(GOLDEN) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            i, re, im = ln.split()
+            idx.append(int(i))
+            vals.append(complex(float(re), float(im)))
+    return np.array(idx, dtype=np.int64), np.array(vals, dtype=np.complex128)
+
+
+def gather(sv, logical_idx):
+    import torch
+    lay = sv.layout()
+    y = np.zeros_like(logical_idx)
+    for q, pos in enumerate(lay):
+        y |= ((logical_idx >> q) & 1) << int(pos)
+    sv.sync()
+    return sv.amps[torch.from_numpy(y).to(sv.amps.device)].cpu().numpy().astype(np.complex128)
+
+
+def plan_for(P, gates, which):
+    if which == "learned":
+        from paper_2608_16940_amd import costmodel as C
+        params, _ = C.load()
+        return P.Plan.learned(N, gates, params)
+    return P.Plan.greedy(N, gates, which)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("which", [6, 7, "learned"])
+def test_wide_blocks_against_oracle_samples(P, which, prec):
+    idx, ref = read_golden()
+    gates = W.brickwork(N, 16, 0)
+    plan = plan_for(P, gates, which)
+    ks = [b["k"] for b in plan.blocks()]
+    if which != "learned":
+        assert max(ks) == which
+    sv = P.StateVector(N)
+    sv.set_precision(prec)
+    before = sv.stats()["by_variant"][3]
+    plan.run(sv)
+    mfma = sv.stats()["by_variant"][3] - before
+    got = gather(sv, idx)
+    d = np.abs(got - ref)
+    rel = float(np.sqrt(np.sum(d ** 2) / np.sum(np.abs(ref) ** 2)))
+    say("n28 %s %s: %d blocks (max k %d, %d mfma) max|d| %.3e rel_l2(sample) %.3e"
+        % (which, prec, len(ks), max(ks), mfma, d.max(), rel))
+    assert mfma >= sum(1 for k in ks if k >= 5)
+    assert d.max() <= 1e-5
+    assert rel <= 1e-5
+    assert abs(sv.norm() - 1) <= 1e-5
+    sv.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_echo_k7(P, prec):
+    gates = W.brickwork(N, 16, 0)
+    fwd = P.Plan.greedy(N, gates, 7)
+    inv = P.Plan.greedy(N, W.inverse(gates), 7)
+    sv = P.StateVector(N)
+    sv.set_precision(prec)
+    fwd.run(sv)
+    inv.run(sv)
+    f0 = abs(gather(sv, np.array([0], dtype=np.int64))[0]) ** 2
+    say("echo n28 k7 %s: fidelity %.9f" % (prec, f0))
+    assert f0 >= 1 - 1e-5
+    sv.close()
