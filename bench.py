@@ -305,12 +305,13 @@ def bench_learned(args):
         bwd.run(sv)
         sv.sync()
         a0 = sv.amps[0].item()
-        echo = abs(a0) ** 2
+        nrm = sv.norm()
+        echo = abs(a0) ** 2 / nrm  # overlap of normalized states
         ks = {}
         for b in fwd.blocks():
             ks[str(b["k"])] = ks.get(str(b["k"]), 0) + 1
         res[name] = {"blocks": len(fwd), "blocks_by_k": ks, "plan_s": plan_s, "execute_s": ex,
-                     "end_to_end_s": plan_s + ex, "echo_fidelity": echo, "layout_identity":
+                     "end_to_end_s": plan_s + ex, "echo_fidelity": echo, "norm_minus_1": nrm - 1, "layout_identity":
                      bool(np.array_equal(sv.layout(), np.arange(n)))}
     sv.close()
     g, l = res["greedy"], res["learned"]

@@ -31,7 +31,9 @@
 // relabels bits inside the tile for free (the lazy relabel L' = alpha o L of
 // Algorithm 2, restricted to the tile's bits).  Without a gate the same
 // structure is an in-place bit permutation in one sweep (k_tile_permute).
+#include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "sv_internal.h"
 
@@ -378,7 +380,9 @@ void fill_args(const TilePlan &tp, int nt, int chunks, float2 *psi, const void *
 
 // One tile per workgroup: the dispatcher then walks memory in order, which
 // measured faster than persistent workgroups striding over the state.
-unsigned grid_of(int64_t ntiles) { return unsigned(ntiles > 0x7fffffff ? 0x7fffffff : ntiles); }
+// A dispatch holds at most 2^32 - 1 work-items: 2^22 workgroups of 256 stay
+// well inside it; the kernels loop over the remaining tiles.
+unsigned grid_of(int64_t ntiles) { return unsigned(ntiles > (int64_t(1) << 22) ? (int64_t(1) << 22) : ntiles); }
 
 template <int K, int M, int PREC, int OPS>
 hipError_t tile_mfma_k(const TilePlan &tp, float2 *psi, const void *op, hipStream_t st) {
@@ -413,6 +417,78 @@ float host_bf16_to_f(uint16_t h) {
   float f;
   std::memcpy(&f, &u, 4);
   return f;
+}
+
+// bf16 neighbour of h one unit in the last place toward +inf (dir > 0) or -inf.
+uint16_t bf16_step(uint16_t h, int dir) {
+  const bool neg = (h & 0x8000u) != 0;
+  const uint16_t mag = h & 0x7FFFu;
+  if (mag == 0) return uint16_t(dir > 0 ? 0x0001u : 0x8001u);
+  return uint16_t((dir > 0) != neg ? h + 1 : h - 1);
+}
+
+// Split every component of G into bf16 hi + lo (round to nearest), then move
+// a few lo values to their other bf16 neighbour (each stays within one unit
+// of its exact residual) so that each column of hi + lo has the column norm
+// of G in FP64.  Without this the split matrix's small departure from
+// unitarity, sum_r |g'_rc|^2 != sum_r |g_rc|^2, is coherent within a fused
+// block and shows as a norm drift that grows linearly with the number of
+// sweeps; with it diag(G'^H G') matches diag(G^H G) to far below one unit.
+// Out: hr, lr, hi_, li indexed r * D + c.
+void split_bf16x3(int D, const double *G, uint16_t *hr, uint16_t *lr, uint16_t *hi_, uint16_t *li) {
+  std::vector<double> val(2 * size_t(D)), hv(2 * size_t(D));
+  std::vector<uint16_t> l16(2 * size_t(D));
+  std::vector<char> used(2 * size_t(D));
+  for (int c = 0; c < D; ++c) {
+    double want = 0, have = 0;
+    for (int r = 0; r < D; ++r)
+      for (int part = 0; part < 2; ++part) {
+        const int j = 2 * r + part;
+        const double v = part ? im_of(G, D, r, c) : re_of(G, D, r, c);
+        const uint16_t h = host_bf16_rne(float(v));
+        const double hd = host_bf16_to_f(h);
+        const uint16_t l = host_bf16_rne(float(v - hd));
+        (part ? hi_ : hr)[r * D + c] = h;
+        val[j] = v;
+        hv[j] = hd;
+        l16[j] = l;
+        used[j] = 0;
+        want += v * v;
+        const double e = hd + double(host_bf16_to_f(l));
+        have += e * e;
+      }
+    // greedy: take the re-rounding that brings the column norm closest to want
+    for (int it = 0; it < 2 * D; ++it) {
+      const double err = have - want;
+      int best = -1;
+      double best_abs = std::fabs(err), best_delta = 0;
+      uint16_t best_l = 0;
+      for (int j = 0; j < 2 * D; ++j) {
+        if (used[j]) continue;
+        const double t = val[j] - hv[j];
+        const double lcur = host_bf16_to_f(l16[j]);
+        if (lcur == t) continue;  // exact: nothing to trade
+        const uint16_t alt = bf16_step(l16[j], t > lcur ? 1 : -1);
+        const double lalt = host_bf16_to_f(alt);
+        const double e0 = hv[j] + lcur, e1 = hv[j] + lalt;
+        const double delta = e1 * e1 - e0 * e0;
+        if (std::fabs(err + delta) < best_abs) {
+          best_abs = std::fabs(err + delta);
+          best = j;
+          best_delta = delta;
+          best_l = alt;
+        }
+      }
+      if (best < 0) break;
+      l16[best] = best_l;
+      used[best] = 1;
+      have += best_delta;
+    }
+    for (int r = 0; r < D; ++r) {
+      lr[r * D + c] = l16[2 * r];
+      li[r * D + c] = l16[2 * r + 1];
+    }
+  }
 }
 
 // Output-row order that makes accumulator register r of lane half h hold row
@@ -498,17 +574,29 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out) {
         for (int l = 0; l < 64; ++l)
           o[(mt * HALF + kk) * 64 + l] = float(embedded(G, K, out_row(HALF, mt, l & 31), HALF * (l >> 5) + kk));
   } else {
-    // embedding split in bf16 hi and lo planes; four consecutive reductions per step
+    // embedding [[Re, -Im], [Im, Re]] of the split planes (split_bf16x3), hi
+    // and lo planes; four consecutive reductions per step
     const int KQ = HALF / 4;
     uint16_t *hi = static_cast<uint16_t *>(out);
     uint16_t *lo = hi + size_t(EMT) * KQ * 64 * 4;
+    std::vector<uint16_t> sp(4 * size_t(D) * D);
+    uint16_t *hr = sp.data(), *lr = hr + D * D, *hm = lr + D * D, *lm = hm + D * D;
+    split_bf16x3(D, G, hr, lr, hm, lm);
     for (int mt = 0; mt < EMT; ++mt)
       for (int kk = 0; kk < KQ; ++kk)
         for (int l = 0; l < 64; ++l)
           for (int e = 0; e < 4; ++e) {
-            const double v = embedded(G, K, out_row(HALF, mt, l & 31), HALF * (l >> 5) + 4 * kk + e);
-            const uint16_t h16 = host_bf16_rne(float(v));
-            const uint16_t l16 = host_bf16_rne(float(v - double(host_bf16_to_f(h16))));
+            const int orow = out_row(HALF, mt, l & 31), icol = HALF * (l >> 5) + 4 * kk + e;
+            const int r = orow >> 1, po = orow & 1, c = icol >> 1, pi = icol & 1;
+            uint16_t h16, l16;
+            if (po == pi) {
+              h16 = hr[r * D + c];
+              l16 = lr[r * D + c];
+            } else {
+              const uint16_t sgn = (po == 0) ? 0x8000u : 0;  // -Im in the upper right block
+              h16 = hm[r * D + c] ^ sgn;
+              l16 = lm[r * D + c] ^ sgn;
+            }
             const size_t idx = ((size_t(mt) * KQ + kk) * 64 + l) * 4 + e;
             hi[idx] = h16;
             lo[idx] = l16;
