@@ -17,6 +17,7 @@
 //       T1 = Gr Xr, T2 = Gi Xi, T3 = (Gr + Gi)(Xr + Xi),
 //       Re y = T1 - T2, Im y = T3 - T1 - T2,
 //     three 2^K x 2^K real GEMMs, 25% fewer MFMA cycles than the embedding;
+//     only Gr and Gi are stored, Gr + Gi is one VALU add per step;
 //   * BF16x3 (any k): the embedding with each operand split x = hi + lo in
 //     bf16 and hi*hi + hi*lo + lo*hi accumulated in FP32
 //     (v_mfma_f32_32x32x8bf16_1k); G is split once on the host from FP64.
@@ -102,17 +103,19 @@ template <int K, int PREC>
 struct Scheme {
   static constexpr int alg = (PREC == SV_PREC_BF16X3) ? ALG_EMBED_BF16X3 : (K >= 5 ? ALG_GAUSS_F32 : ALG_EMBED_F32);
   // operand bytes (see pack_mfma_operand)
-  static constexpr int bytes = (alg == ALG_GAUSS_F32) ? 3 * (1 << (2 * K + 2)) : (1 << (2 * K + 4));
+  static constexpr int bytes = (alg == ALG_GAUSS_F32) ? 2 * (1 << (2 * K + 2)) : (1 << (2 * K + 4));
 };
 
-// Occupancy target per gate width (waves per SIMD the register budget is cut for).
-template <int K>
+// Occupancy target (waves per SIMD the register budget is cut for).  FP32
+// k=5 with the operand in LDS fits four 40 KiB workgroups per CU in 125
+// VGPRs; the other k=5 forms would spill at that budget and keep three.
+template <int K, int PREC, int OPS>
 struct WavesPerSimd {
-  static constexpr int value = K <= 4 ? 4 : (K == 5 ? 3 : 2);
+  static constexpr int value = K <= 4 ? 4 : (K == 5 ? ((PREC == SV_PREC_FP32 && OPS == OP_LDS) ? 4 : 3) : 2);
 };
 
 template <int K, int M, int PREC, int OPS>
-__global__ __launch_bounds__(256, WavesPerSimd<K>::value) void k_tile_mfma(TileArgs a) {
+__global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_tile_mfma(TileArgs a) {
   constexpr int NT = 256;               // four waves for every gate width
   constexpr int S = K + M;
   constexpr int TILE = 1 << S;
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(256, WavesPerSimd<K>::value) void k_tile_mfma(TileA
 
     if constexpr (ALG == ALG_GAUSS_F32) {
       // step kk uses amplitude (AH h + kk) of this lane's group
-      constexpr int UNR = (K <= 5) ? AH : 8;
+      constexpr int UNR = 8;
 #pragma unroll UNR
       for (int kk = 0; kk < AH; ++kk) {
         const float2 x = lds[swz<K>(gbase | (h * AH + kk))];
@@ -215,8 +218,9 @@ __global__ __launch_bounds__(256, WavesPerSimd<K>::value) void k_tile_mfma(TileA
           acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(opv((0 * MTT + mt) * AH + kk), x.x, acc[j], 0, 0, 0);
           acc[MPW + j] =
               __builtin_amdgcn_mfma_f32_32x32x2f32(opv((1 * MTT + mt) * AH + kk), x.y, acc[MPW + j], 0, 0, 0);
-          acc[2 * MPW + j] =
-              __builtin_amdgcn_mfma_f32_32x32x2f32(opv((2 * MTT + mt) * AH + kk), xs, acc[2 * MPW + j], 0, 0, 0);
+          // third Gauss operand Gr + Gi formed here: two planes keep the k=5 workgroup at 40 KiB of LDS
+          acc[2 * MPW + j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+              opv((0 * MTT + mt) * AH + kk) + opv((1 * MTT + mt) * AH + kk), xs, acc[2 * MPW + j], 0, 0, 0);
         }
       }
       if constexpr (SHARED_GROUPS) __syncthreads();  // sibling waves finished reading these groups
@@ -544,7 +548,7 @@ bool make_gate_tile(int n, int K, const int32_t *A, uint64_t extra, TilePlan *tp
 }
 
 size_t mfma_operand_bytes(int K, int prec) {
-  if (prec == SV_PREC_FP32 && K >= 5) return size_t(3) << (2 * K + 2);
+  if (prec == SV_PREC_FP32 && K >= 5) return size_t(2) << (2 * K + 2);
   return size_t(1) << (2 * K + 4);
 }
 
@@ -553,17 +557,17 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out) {
   const int HALF = 1 << K, AH = 1 << (K - 1);
   const int EMT = (2 << K) / 32;
   if (prec == SV_PREC_FP32 && K >= 5) {
-    // three planes Gr, Gi, Gr + Gi; plane x, tile mt, step kk, lane l holds
+    // two planes Gr, Gi (the kernel forms Gr + Gi); plane x, tile mt, step kk, lane l holds
     // X[out_row(AH, mt, l % 32)][AH * (l / 32) + kk]
     const int GMT = D / 32;
     float *o = static_cast<float *>(out);
-    for (int x = 0; x < 3; ++x)
+    for (int x = 0; x < 2; ++x)
       for (int mt = 0; mt < GMT; ++mt)
         for (int kk = 0; kk < AH; ++kk)
           for (int l = 0; l < 64; ++l) {
             const int r = out_row(AH, mt, l & 31), c = AH * (l >> 5) + kk;
             const double gr = re_of(G, D, r, c), gi = im_of(G, D, r, c);
-            const double val = (x == 0) ? gr : (x == 1 ? gi : gr + gi);
+            const double val = (x == 0) ? gr : gi;
             o[((x * GMT + mt) * AH + kk) * 64 + l] = float(val);
           }
   } else if (prec == SV_PREC_FP32) {
