@@ -80,7 +80,10 @@ int sv_reset(sv_state *s);
  *   targets  host pointer, k distinct LOGICAL qubits in [0, N)
  *   k        1 <= k <= min(N, SV_MAX_K)
  * The call may change the layout map (lazy relabel, L' = alpha o L); read it
- * with sv_get_layout.  Unitarity is not checked.
+ * with sv_get_layout.  A matrix whose off-diagonal entries are all exactly
+ * zero takes the streaming diagonal lowering (Algorithm 2, diag branch):
+ * one pass multiplying each amplitude by the entry its target bits select,
+ * layout unchanged.  Unitarity is not checked.
  * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED, SV_ERR_DEVICE.
  */
 int sv_apply_fused(sv_state *s, const double *matrix, const int32_t *targets, int k);
@@ -142,7 +145,8 @@ const char *sv_last_error(void);
 #define SV_VARIANT_VALU 1    /* per-thread group gather / FMA / scatter, k <= 4 */
 #define SV_VARIANT_SHUFFLE 2 /* k = 1 on a physical bit < 7, wavefront shuffle */
 #define SV_VARIANT_MFMA 3    /* LDS-tiled real-embedded complex GEMM on MFMA, 4 <= k <= 7 */
-#define SV_VARIANT_GENERIC 4 /* one group per workgroup, any k <= 10 */
+#define SV_VARIANT_GENERIC 4 /* one group per workgroup, any k <= 8 */
+#define SV_VARIANT_DIAG 5    /* diagonal matrices only: streaming elementwise multiply, any k <= 8 */
 
 /* Arithmetic of the MFMA lowering. */
 #define SV_OPT_PRECISION 2
@@ -189,7 +193,7 @@ typedef struct sv_stats {
   int64_t swap_half_sweeps; /* single bit-transposition passes (half of the state moves) */
   int64_t relabels;         /* target bits moved down by the lazy relabel */
   int64_t launches;         /* kernels launched by gate and layout calls */
-  int64_t by_variant[5];    /* gate applications per SV_VARIANT_* */
+  int64_t by_variant[6];    /* gate applications per SV_VARIANT_* */
   int64_t permute_sweeps;   /* full-sweep tile permutation passes */
 } sv_stats;
 int sv_get_stats(const sv_state *s, sv_stats *out);

@@ -11,7 +11,9 @@
  *   targets      concatenated ordered logical targets (sum ks entries)
  *   mats         concatenated complex128 row-major interleaved matrices
  *                (2 * 4^ks[i] doubles each), little-endian in the targets
- *   diag         optional (may be NULL) per-gate flag: 1 if the matrix is diagonal
+ *   diag         optional (may be NULL) per-gate flag: 1 if the matrix is diagonal.
+ *                The planner marks a gate diagonal when its matrix is exactly
+ *                diagonal; a flag of 1 on a non-diagonal matrix is SV_ERR_ARG.
  * Plans are host objects owned by the library until sv_plan_free.
  */
 #ifndef SV_PLAN_H_
@@ -61,9 +63,14 @@ int sv_plan_greedy(int n_qubits, int n_gates, const int32_t *ks, const int32_t *
  * taking at each step the ready gate that enlarges the cluster's qubit set
  * least (earliest on ties) while it stays within max(k_max, diag_max). */
 #define SV_PLAN_REORDER 1
-/* flags: SV_PLAN_SEARCH_CAP (learned score only) plans with every width cap
- * from 4 to k_max and keeps the plan of least predicted total time. */
+/* flags: SV_PLAN_SEARCH_CAP (learned score only) plans with every dense
+ * width cap c from 4 to k_max, each with diagonal cap min(c, diag_max) and
+ * diag_max, and keeps the plan of least predicted total time. */
 #define SV_PLAN_SEARCH_CAP 2
+/* flags: SV_PLAN_REPEAT runs the reorder-and-fuse pipeline again on the
+ * emitted blocks, at most four rounds in all, stopping when the block count
+ * no longer decreases (Section IV-C). */
+#define SV_PLAN_REPEAT 4
 int sv_plan_dp(int n_qubits, int n_gates, const int32_t *ks, const int32_t *targets, const double *mats,
                const int8_t *diag, int k_max, int diag_max, int window, int score, const float *mlp_params_host,
                int mlp_nin, int mlp_hid, int flags, sv_plan **out);
@@ -71,11 +78,10 @@ int sv_plan_dp(int n_qubits, int n_gates, const int32_t *ks, const int32_t *targ
 /*
  * Cost-model features of one fused sweep (SV_MLP_FEATURES floats): N/35,
  * k/8, the k physical target positions sorted ascending divided by 35 and
- * padded with -0.25 to seven slots, and the structural zero fraction of the
- * block (1 - 2^-k when every gate is diagonal or a scaled permutation,
- * else 0).  monomial: 1 if every gate has one non-zero per row.
+ * padded with -0.25 to seven slots, and 1 if the block is diagonal (it then
+ * takes the streaming diagonal lowering) else 0.
  */
-int sv_cost_features(int n_qubits, int k, const int32_t *phys_targets, int monomial, float *out);
+int sv_cost_features(int n_qubits, int k, const int32_t *phys_targets, int diagonal, float *out);
 
 /* Number of fused blocks. */
 int sv_plan_num_blocks(const sv_plan *p, int *out);

@@ -202,10 +202,12 @@ class Plan:
 
     @classmethod
     def dp(cls, n: int, gates, k_max: int = 5, diag_max: int = 6, window: int = 64, params=None,
-           nin: int = 10, hid: int = 64, reorder: bool = False, search_cap: bool = False) -> "Plan":
+           nin: int = 10, hid: int = 64, reorder: bool = False, search_cap: bool = False,
+           repeat: bool = False) -> "Plan":
         """Windowed DP fusion: paper score (params None) or learned sweep-time score (MLP params);
         reorder=True first applies the commute-aware reorder; search_cap=True lets the learned
-        score pick the width cap (4..k_max)."""
+        score pick the dense width cap (4..k_max); repeat=True reruns reorder-and-fuse on the
+        blocks, at most four rounds in all."""
         ks, tg, mats, dg = cls._flat(gates)
         h = ctypes.c_void_p()
         if params is None:
@@ -218,14 +220,21 @@ class Plan:
                                tg.ctypes.data_as(_native._i32p), mats.ctypes.data_as(_native._dp),
                                dg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), int(k_max), int(diag_max),
                                int(window), score, pp, int(nin), int(hid),
-                               (1 if reorder else 0) | (2 if search_cap else 0), ctypes.byref(h)))
+                               (1 if reorder else 0) | (2 if search_cap else 0) | (4 if repeat else 0),
+                               ctypes.byref(h)))
         return cls(h, int(n))
 
     @classmethod
+    def paper(cls, n: int, gates, k_max: int = 6, diag_max: int = 6, window: int = 64) -> "Plan":
+        """The paper's pipeline (Section IV-C): commute-aware reorder, windowed DP on the 4^k / 1
+        score, cross-window merge, repeated up to four rounds; caps as the paper's GPU runs use."""
+        return cls.dp(n, gates, k_max=k_max, diag_max=diag_max, window=window, reorder=True, repeat=True)
+
+    @classmethod
     def learned(cls, n: int, gates, params, k_max: int = 7, window: int = 64) -> "Plan":
-        """The learned planner: commute-aware reorder + DP on predicted sweep times, cap chosen by the model."""
+        """The learned planner: the same pipeline on predicted sweep times, dense cap chosen by the model."""
         return cls.dp(n, gates, k_max=k_max, diag_max=k_max, window=window, params=params, reorder=True,
-                      search_cap=True)
+                      search_cap=True, repeat=True)
 
     def __len__(self) -> int:
         v = ctypes.c_int()

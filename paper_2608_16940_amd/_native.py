@@ -28,7 +28,7 @@ OPT_POLICY = 7
 POLICY = {"belady": 0, "first_free": 1, "lru": 2}
 MFMA_OPERAND = {"regs": 0, "lds": 1, "global": 2, "auto": 3}
 
-VARIANT = {"auto": 0, "valu": 1, "shuffle": 2, "mfma": 3, "generic": 4}
+VARIANT = {"auto": 0, "valu": 1, "shuffle": 2, "mfma": 3, "generic": 4, "diag": 5}
 PRECISION = {"fp32": 0, "bf16x3": 1}
 
 
@@ -41,7 +41,7 @@ class SvError(RuntimeError):
 class sv_stats(ctypes.Structure):
     _fields_ = [("gate_sweeps", ctypes.c_int64), ("swap_half_sweeps", ctypes.c_int64),
                 ("relabels", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("by_variant", ctypes.c_int64 * 5), ("permute_sweeps", ctypes.c_int64)]
+                ("by_variant", ctypes.c_int64 * 6), ("permute_sweeps", ctypes.c_int64)]
 
 
 class sv_batch_circuit(ctypes.Structure):

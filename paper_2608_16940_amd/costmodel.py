@@ -36,10 +36,10 @@ def param_count(nin: int = NIN, hid: int = HID) -> int:
     return int(lib().sv_mlp_param_count(nin, hid))
 
 
-def features(n: int, targets, monomial: bool) -> np.ndarray:
+def features(n: int, targets, diagonal: bool) -> np.ndarray:
     t = np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
     out = np.zeros(NIN, dtype=np.float32)
-    check(lib().sv_cost_features(int(n), int(t.size), t.ctypes.data_as(_native._i32p), 1 if monomial else 0,
+    check(lib().sv_cost_features(int(n), int(t.size), t.ctypes.data_as(_native._i32p), 1 if diagonal else 0,
                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
     return out
 
@@ -171,7 +171,7 @@ def _random_block(rng, n, k, kind):
         m = np.diag(ph)
         if kind == "perm":
             m = m[rng.permutation(d)]
-    return t, np.ascontiguousarray(m, dtype=np.complex128), kind != "dense"
+    return t, np.ascontiguousarray(m, dtype=np.complex128), kind == "diag"
 
 
 def collect(n_values, samples_per_n, seed: int = 0, reps: int = 3, device="cuda:0", log=None):
@@ -192,8 +192,8 @@ def collect(n_values, samples_per_n, seed: int = 0, reps: int = 3, device="cuda:
         t0 = time.perf_counter()
         for _ in range(int(cnt)):
             k = int(rng.choice([1, 2, 3, 4, 5, 6, 7], p=[0.08, 0.12, 0.14, 0.2, 0.24, 0.12, 0.1]))
-            kind = str(rng.choice(["dense", "diag", "perm"], p=[0.8, 0.1, 0.1]))
-            t, m, mono = _random_block(rng, int(n), k, kind)
+            kind = str(rng.choice(["dense", "diag", "perm"], p=[0.7, 0.2, 0.1]))
+            t, m, is_diag = _random_block(rng, int(n), k, kind)
             sv.apply(m, t)
             times = []
             for _ in range(reps):
@@ -206,7 +206,7 @@ def collect(n_values, samples_per_n, seed: int = 0, reps: int = 3, device="cuda:
             # features use the physical targets at the time of the sweep
             L = sv.layout()
             phys = [int(L[q]) for q in t]
-            Xs.append(features(int(n), phys, mono))
+            Xs.append(features(int(n), phys, is_diag))
             ys.append(math.log(ms) - (int(n) - 30) * math.log(2.0))
             rows.append((int(n), k, phys, kind, ms))
         if log:

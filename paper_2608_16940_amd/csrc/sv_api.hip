@@ -191,8 +191,18 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
   const bool shuffle_ok = (k == 1 && A[0] <= 6);
   const bool mfma_ok = (k >= 4 && k <= 7 && n >= k + mfma_tile_M(k));
   const bool valu_ok = (k <= 4);
+  const int D = 1 << k;
+  bool diag = true;  // every off-diagonal entry exactly zero
+  for (int r = 0; r < D && diag; ++r)
+    for (int c = 0; c < D; ++c)
+      if (r != c && (matrix[2 * (r * D + c)] != 0.0 || matrix[2 * (r * D + c) + 1] != 0.0)) {
+        diag = false;
+        break;
+      }
   if (v == SV_VARIANT_AUTO) {
-    if (shuffle_ok)
+    if (diag)
+      v = SV_VARIANT_DIAG;
+    else if (shuffle_ok)
       v = SV_VARIANT_SHUFFLE;
     else if (mfma_ok && k >= s->mfma_min_k)
       v = SV_VARIANT_MFMA;
@@ -201,9 +211,27 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
     else
       v = SV_VARIANT_GENERIC;
   }
-  const int D = 1 << k;
   hipError_t e = hipSuccess;
   switch (v) {
+    case SV_VARIANT_DIAG: {
+      if (!diag) {
+        set_error("diagonal lowering needs a diagonal matrix");
+        return SV_ERR_UNSUPPORTED;
+      }
+      std::vector<float2> d(static_cast<size_t>(D));
+      for (int r = 0; r < D; ++r)
+        d[r] = make_float2(float(matrix[2 * (r * D + r)]), float(matrix[2 * (r * D + r) + 1]));
+      void *dev = nullptr;
+      int slot = 0;
+      int rc = stage(s, d.data(), d.size() * sizeof(float2), &dev, &slot);
+      if (rc) return rc;
+      e = launch_diag(s->amps, n, k, A, static_cast<const float2 *>(dev), s->st);
+      if (e == hipSuccess) {
+        rc = release_slot(s, slot);
+        if (rc) return rc;
+      }
+      break;
+    }
     case SV_VARIANT_SHUFFLE:
     case SV_VARIANT_VALU: {
       if ((v == SV_VARIANT_SHUFFLE && !shuffle_ok) || (v == SV_VARIANT_VALU && !valu_ok)) {
@@ -285,7 +313,7 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
   }
   s->stats.gate_sweeps += 1;
   s->stats.launches += 1;
-  if (v >= 0 && v < 5) s->stats.by_variant[v] += 1;
+  if (v >= 0 && v < 6) s->stats.by_variant[v] += 1;
   return SV_OK;
 }
 
@@ -666,7 +694,7 @@ int sv_set_option(sv_state *s, int key, int value) {
   }
   switch (key) {
     case SV_OPT_VARIANT:
-      if (value < SV_VARIANT_AUTO || value > SV_VARIANT_GENERIC) break;
+      if (value < SV_VARIANT_AUTO || value > SV_VARIANT_DIAG) break;
       s->variant = value;
       return SV_OK;
     case SV_OPT_PRECISION:

@@ -34,20 +34,15 @@ struct GateView {
   int k;
   const int32_t *t;
   const double *m;
-  bool diag;
-  bool monomial;  // one non-zero per row (diagonal or scaled permutation)
+  bool diag;       // eligible for the streaming diagonal lowering: matrix exactly diagonal
+  int weight = 1;  // input gates this view stands for (a block of an earlier round)
 };
 
-bool is_monomial(const double *m, int k) {
+bool is_diagonal(const double *m, int k) {
   const int d = 1 << k;
-  double mx = 0;
-  for (int i = 0; i < d * d; ++i) mx = std::max(mx, std::hypot(m[2 * i], m[2 * i + 1]));
-  for (int r = 0; r < d; ++r) {
-    int nz = 0;
+  for (int r = 0; r < d; ++r)
     for (int c = 0; c < d; ++c)
-      if (std::hypot(m[2 * (r * d + c)], m[2 * (r * d + c) + 1]) > 1e-12 * mx) ++nz;
-    if (nz != 1) return false;
-  }
+      if (r != c && (m[2 * (r * d + c)] != 0.0 || m[2 * (r * d + c) + 1] != 0.0)) return false;
   return true;
 }
 
@@ -102,7 +97,8 @@ SvBlock make_block(const std::vector<GateView> &gates) {
       if (std::find(b.tuple.begin(), b.tuple.end(), g.t[j]) == b.tuple.end()) b.tuple.push_back(g.t[j]);
   std::sort(b.tuple.begin(), b.tuple.end());
   b.k = int(b.tuple.size());
-  b.ngates = int(gates.size());
+  b.ngates = 0;
+  for (const auto &g : gates) b.ngates += g.weight;
   const int D = 1 << b.k;
   b.matrix.assign(size_t(2) * D * D, 0.0);
   for (int i = 0; i < D; ++i) b.matrix[2 * (size_t(i) * D + i)] = 1.0;
@@ -125,7 +121,11 @@ bool parse_gates(int n, int ngates, const int32_t *ks, const int32_t *targets, c
       for (int a = 0; a < j; ++a)
         if (t[a] == t[j]) return false;
     }
-    out->push_back(GateView{k, t, mats + moff, diag ? diag[i] != 0 : false, is_monomial(mats + moff, k)});
+    // the marker is conservative: a gate is diagonal when its matrix is; a
+    // caller flag that claims a non-diagonal matrix is an error
+    const bool d = is_diagonal(mats + moff, k);
+    if (diag && diag[i] != 0 && !d) return false;
+    out->push_back(GateView{k, t, mats + moff, d, 1});
     toff += size_t(k);
     moff += size_t(2) << (2 * k);
   }
@@ -241,7 +241,7 @@ int sv_plan_free(sv_plan *p) {
   return SV_OK;
 }
 
-int sv_cost_features(int n, int k, const int32_t *A, int monomial, float *out) {
+int sv_cost_features(int n, int k, const int32_t *A, int diagonal, float *out) {
   if (!A || !out || k < 1 || k > 7 || n < 1 || n > SV_MAX_QUBITS) {
     sv::set_error("bad feature argument");
     return SV_ERR_ARG;
@@ -252,7 +252,7 @@ int sv_cost_features(int n, int k, const int32_t *A, int monomial, float *out) {
   out[0] = float(n) / 35.f;
   out[1] = float(k) / 8.f;
   for (int j = 0; j < 7; ++j) out[2 + j] = (j < k) ? float(s[j]) / 35.f : -0.25f;
-  out[9] = monomial ? float(1.0 - std::ldexp(1.0, -k)) : 0.f;
+  out[9] = diagonal ? 1.f : 0.f;
   return SV_OK;
 }
 
@@ -265,18 +265,18 @@ struct Scorer {
   int n;
   const float *params;
   int nin, hid;
-  std::map<std::vector<int32_t>, double> cache;  // (k, mono, sorted targets...) -> Gamma
+  std::map<std::vector<int32_t>, double> cache;  // (sorted targets..., diag) -> Gamma
 
-  double operator()(const std::vector<int32_t> &tuple_sorted, bool all_diag, bool all_mono) {
+  double operator()(const std::vector<int32_t> &tuple_sorted, bool all_diag) {
     const int k = int(tuple_sorted.size());
     if (score == SV_SCORE_PAPER) return all_diag ? 1.0 : std::ldexp(1.0, 2 * k);
     if (k > 7) return 1e30;
     std::vector<int32_t> key(tuple_sorted);
-    key.push_back(all_mono ? 1 : 0);
+    key.push_back(all_diag ? 1 : 0);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     float f[SV_MLP_FEATURES];
-    sv_cost_features(n, k, tuple_sorted.data(), all_mono ? 1 : 0, f);
+    sv_cost_features(n, k, tuple_sorted.data(), all_diag ? 1 : 0, f);
     double y = 0;
     sv_mlp_forward_host(params, nin, hid, f, 1, &y);
     // the model predicts log(ms) at N = 30 scale; a sweep's time grows as 2^N
@@ -290,16 +290,13 @@ struct Span {
   size_t a, b;  // gates [a, b)
 };
 
-void span_info(const std::vector<GateView> &gates, size_t a, size_t b, std::vector<int32_t> *tuple, bool *diag,
-               bool *mono) {
+void span_info(const std::vector<GateView> &gates, size_t a, size_t b, std::vector<int32_t> *tuple, bool *diag) {
   tuple->clear();
   *diag = true;
-  *mono = true;
   for (size_t g = a; g < b; ++g) {
     for (int j = 0; j < gates[g].k; ++j)
       if (std::find(tuple->begin(), tuple->end(), gates[g].t[j]) == tuple->end()) tuple->push_back(gates[g].t[j]);
     *diag = *diag && gates[g].diag;
-    *mono = *mono && gates[g].monomial;
   }
   std::sort(tuple->begin(), tuple->end());
 }
@@ -367,65 +364,22 @@ std::vector<size_t> commute_order(const std::vector<GateView> &gates, int n, int
 }  // namespace
 
 namespace {
-sv_plan *plan_dp_once(int n, const std::vector<GateView> &input, int k_max, int diag_max, int window, int score,
-                      const float *mlp_params, int mlp_nin, int mlp_hid, int flags, double *predicted);
-}
 
-extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
-                          const int8_t *diag, int k_max, int diag_max, int window, int score,
-                          const float *mlp_params, int mlp_nin, int mlp_hid, int flags, sv_plan **out) {
-  if (!out || ngates < 0 || (ngates > 0 && (!ks || !targets || !mats)) || k_max < 1 || k_max > 8 ||
-      diag_max < 1 || diag_max > 8 || window < 1 || n < SV_MIN_QUBITS || n > SV_MAX_QUBITS ||
-      (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED) ||
-      (score == SV_SCORE_LEARNED && (!mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1))) {
-    sv::set_error("bad dp planner argument");
-    return SV_ERR_ARG;
-  }
+// One reorder-and-fuse pass over `views`: the optional commute-aware reorder,
+// the windowed DP (Eq. dp-recurrence) and the cross-window greedy merge.
+// Returns the partition as lists of view indices in application order and
+// the total score.  Views of later rounds carry no matrix: only k, targets,
+// the diagonal marker and the weight are read here.
+std::vector<std::vector<size_t>> dp_pass(int n, const std::vector<GateView> &views, int k_max, int diag_max,
+                                         int window, int flags, Scorer &gamma, double *predicted) {
+  std::vector<size_t> order(views.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  if (flags & SV_PLAN_REORDER) order = commute_order(views, n, std::max(k_max, diag_max));
   std::vector<GateView> gates;
-  if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
-    sv::set_error("bad gate in list");
-    return SV_ERR_ARG;
-  }
-  if ((flags & SV_PLAN_SEARCH_CAP) && score == SV_SCORE_LEARNED) {
-    // the cost model also picks the width cap: plan with every cap up to
-    // k_max and keep the plan with the lowest predicted total time
-    sv_plan *best = nullptr;
-    double best_t = 1e300;
-    for (int cap = std::min(4, k_max); cap <= k_max; ++cap) {
-      double t = 0;
-      sv_plan *p = plan_dp_once(n, gates, cap, std::min(cap, diag_max), window, score, mlp_params, mlp_nin, mlp_hid,
-                                flags, &t);
-      if (t < best_t) {
-        delete best;
-        best = p;
-        best_t = t;
-      } else {
-        delete p;
-      }
-    }
-    *out = best;
-    return SV_OK;
-  }
-  double t = 0;
-  *out = plan_dp_once(n, gates, k_max, diag_max, window, score, mlp_params, mlp_nin, mlp_hid, flags, &t);
-  return SV_OK;
-}
-
-namespace {
-sv_plan *plan_dp_once(int n, const std::vector<GateView> &input, int k_max, int diag_max, int window, int score,
-                      const float *mlp_params, int mlp_nin, int mlp_hid, int flags, double *predicted) {
-  std::vector<GateView> gates(input);
-  if (flags & SV_PLAN_REORDER) {
-    const std::vector<size_t> order = commute_order(gates, n, std::max(k_max, diag_max));
-    std::vector<GateView> re;
-    re.reserve(gates.size());
-    for (size_t g : order) re.push_back(gates[g]);
-    gates.swap(re);
-  }
-  Scorer gamma{score, n, mlp_params, mlp_nin, mlp_hid, {}};
+  gates.reserve(order.size());
+  for (size_t g : order) gates.push_back(views[g]);
   const int cap_any = std::max(k_max, diag_max);
   std::vector<Span> spans;
-  std::vector<int32_t> tuple;
   for (size_t w0 = 0; w0 < gates.size(); w0 += size_t(window)) {
     const size_t h = std::min(size_t(window), gates.size() - w0);
     std::vector<double> D(h + 1, 0.0);
@@ -434,19 +388,18 @@ sv_plan *plan_dp_once(int n, const std::vector<GateView> &input, int k_max, int 
       double best = 1e300;
       size_t bj = i - 1;
       std::vector<int32_t> set;
-      bool all_diag = true, all_mono = true;
+      bool all_diag = true;
       for (size_t j = i; j-- > 0;) {
         const GateView &g = gates[w0 + j];
         for (int q = 0; q < g.k; ++q)
           if (std::find(set.begin(), set.end(), g.t[q]) == set.end()) set.push_back(g.t[q]);
         all_diag = all_diag && g.diag;
-        all_mono = all_mono && g.monomial;
         const int width = int(set.size());
         const int cap = all_diag ? diag_max : k_max;
         if (width <= cap || j == i - 1) {
           std::vector<int32_t> srt(set);
           std::sort(srt.begin(), srt.end());
-          const double c = D[j] + gamma(srt, all_diag, all_mono);
+          const double c = D[j] + gamma(srt, all_diag);
           if (c < best) {
             best = c;
             bj = j;
@@ -468,30 +421,140 @@ sv_plan *plan_dp_once(int n, const std::vector<GateView> &input, int k_max, int 
     if (!merged.empty()) {
       Span &last = merged.back();
       std::vector<int32_t> t1, t2, tm;
-      bool d1, m1, d2, m2, dm, mm;
-      span_info(gates, last.a, last.b, &t1, &d1, &m1);
-      span_info(gates, sp.a, sp.b, &t2, &d2, &m2);
-      span_info(gates, last.a, sp.b, &tm, &dm, &mm);
+      bool d1, d2, dm;
+      span_info(gates, last.a, last.b, &t1, &d1);
+      span_info(gates, sp.a, sp.b, &t2, &d2);
+      span_info(gates, last.a, sp.b, &tm, &dm);
       const int cap = dm ? diag_max : k_max;
-      if (int(tm.size()) <= cap && gamma(tm, dm, mm) < gamma(t1, d1, m1) + gamma(t2, d2, m2)) {
+      if (int(tm.size()) <= cap && gamma(tm, dm) < gamma(t1, d1) + gamma(t2, d2)) {
         last.b = sp.b;
         continue;
       }
     }
     merged.push_back(sp);
   }
-  sv_plan *p = new sv_plan();
-  p->n = n;
+  std::vector<std::vector<size_t>> out;
+  out.reserve(merged.size());
   double total = 0;
   for (const Span &sp : merged) {
-    std::vector<GateView> seg(gates.begin() + long(sp.a), gates.begin() + long(sp.b));
     std::vector<int32_t> tp;
-    bool dg, mo;
-    span_info(gates, sp.a, sp.b, &tp, &dg, &mo);
-    total += gamma(tp, dg, mo);
-    p->blocks.push_back(make_block(seg));
+    bool dg;
+    span_info(gates, sp.a, sp.b, &tp, &dg);
+    total += gamma(tp, dg);
+    std::vector<size_t> m;
+    for (size_t i = sp.a; i < sp.b; ++i) m.push_back(order[i]);
+    out.push_back(std::move(m));
   }
   *predicted = total;
+  return out;
+}
+
+// A partition of the input gates: each block lists input indices in application order.
+struct Partition {
+  std::vector<std::vector<size_t>> blocks;
+  double predicted = 0;
+};
+
+// The pipeline, and with SV_PLAN_REPEAT up to three more rounds whose views
+// are the previous round's blocks (Section IV-C: at most four rounds,
+// stopping when the block count no longer decreases).  Every round's DP may
+// keep each block of the previous round as a singleton, so the score never
+// rises from round to round.
+Partition dp_rounds(int n, const std::vector<GateView> &gates, int k_max, int diag_max, int window, int flags,
+                    Scorer &gamma) {
+  std::vector<GateView> views(gates);
+  std::vector<std::vector<size_t>> members(gates.size());
+  for (size_t i = 0; i < gates.size(); ++i) members[i] = {i};
+  std::vector<std::vector<int32_t>> tuples;  // target storage of the current round's views
+  Partition best;
+  const int rounds = (flags & SV_PLAN_REPEAT) ? 4 : 1;
+  for (int r = 0; r < rounds; ++r) {
+    double t = 0;
+    const std::vector<std::vector<size_t>> part = dp_pass(n, views, k_max, diag_max, window, flags, gamma, &t);
+    if (r > 0 && part.size() >= views.size()) break;
+    std::vector<std::vector<size_t>> next_members;
+    next_members.reserve(part.size());
+    for (const auto &blk : part) {
+      std::vector<size_t> m;
+      for (size_t v : blk) m.insert(m.end(), members[v].begin(), members[v].end());
+      next_members.push_back(std::move(m));
+    }
+    best.blocks = next_members;
+    best.predicted = t;
+    if (r + 1 == rounds) break;
+    std::vector<std::vector<int32_t>> next_tuples(part.size());
+    std::vector<GateView> next_views;
+    next_views.reserve(part.size());
+    for (size_t b = 0; b < part.size(); ++b) {
+      bool dg = true;
+      int w = 0;
+      for (size_t v : part[b]) {
+        for (int j = 0; j < views[v].k; ++j)
+          if (std::find(next_tuples[b].begin(), next_tuples[b].end(), views[v].t[j]) == next_tuples[b].end())
+            next_tuples[b].push_back(views[v].t[j]);
+        dg = dg && views[v].diag;
+        w += views[v].weight;
+      }
+      std::sort(next_tuples[b].begin(), next_tuples[b].end());
+      next_views.push_back(GateView{int(next_tuples[b].size()), next_tuples[b].data(), nullptr, dg, w});
+    }
+    tuples = std::move(next_tuples);  // the inner buffers (and the views' pointers) stay where they are
+    views = std::move(next_views);
+    members = std::move(next_members);
+  }
+  return best;
+}
+
+sv_plan *build_plan(int n, const std::vector<GateView> &gates, const Partition &part) {
+  sv_plan *p = new sv_plan();
+  p->n = n;
+  p->blocks.reserve(part.blocks.size());
+  for (const auto &blk : part.blocks) {
+    std::vector<GateView> seg;
+    seg.reserve(blk.size());
+    for (size_t g : blk) seg.push_back(gates[g]);
+    p->blocks.push_back(make_block(seg));
+  }
   return p;
 }
 }  // namespace
+
+extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
+                          const int8_t *diag, int k_max, int diag_max, int window, int score,
+                          const float *mlp_params, int mlp_nin, int mlp_hid, int flags, sv_plan **out) {
+  if (!out || ngates < 0 || (ngates > 0 && (!ks || !targets || !mats)) || k_max < 1 || k_max > 8 ||
+      diag_max < 1 || diag_max > 8 || window < 1 || n < SV_MIN_QUBITS || n > SV_MAX_QUBITS ||
+      (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED) ||
+      (score == SV_SCORE_LEARNED && (!mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1))) {
+    sv::set_error("bad dp planner argument");
+    return SV_ERR_ARG;
+  }
+  std::vector<GateView> gates;
+  if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
+    sv::set_error("bad gate in list");
+    return SV_ERR_ARG;
+  }
+  Scorer gamma{score, n, mlp_params, mlp_nin, mlp_hid, {}};  // one cache for every pass
+  if ((flags & SV_PLAN_SEARCH_CAP) && score == SV_SCORE_LEARNED) {
+    // The cost model also picks the caps: plan with every dense cap c up to
+    // k_max, with the diagonal cap at min(c, diag_max) and at diag_max
+    // (diagonal blocks stream at one sweep's cost whatever their width, but
+    // the reorder grows clusters up to the larger cap, which changes the
+    // order), and keep the partition of least predicted time.  Products are
+    // formed for the chosen partition only.
+    Partition best;
+    best.predicted = 1e300;
+    for (int cap = std::min(4, k_max); cap <= k_max; ++cap) {
+      const int lo = std::min(cap, diag_max);
+      for (int dcap : {lo, diag_max}) {
+        Partition part = dp_rounds(n, gates, cap, dcap, window, flags, gamma);
+        if (part.predicted < best.predicted) best = std::move(part);
+        if (diag_max == lo) break;
+      }
+    }
+    *out = build_plan(n, gates, best);
+    return SV_OK;
+  }
+  *out = build_plan(n, gates, dp_rounds(n, gates, k_max, diag_max, window, flags, gamma));
+  return SV_OK;
+}

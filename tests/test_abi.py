@@ -127,3 +127,17 @@ def test_fused_plan_equals_unfused_on_oracle(P):
             oracle.apply_gate(psi, b["matrix"], b["targets"])
         m = oracle.metrics(ref, psi)
         assert m["infidelity"] < 1e-12 and m["max_abs"] < 1e-12, (k_max, m)
+
+
+def test_planner_rejects_false_diagonal_marker(P):
+    """A gate marked diagonal must have an exactly diagonal matrix."""
+    x = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    bad = [W.Gate("x", (0,), x, diag=True)]
+    with pytest.raises(RuntimeError):
+        P.Plan.greedy(3, bad, 2)
+    ok = [W.Gate("rz", (0,), W.rz(0.3), diag=True), W.Gate("cz", (0, 1), W.cz(), diag=True)]
+    plan = P.Plan.greedy(3, ok, 2)
+    assert [b["diag"] for b in plan.blocks()] == [True]
+    # an unmarked diagonal matrix is still found diagonal
+    plan = P.Plan.greedy(3, [W.Gate("d", (1,), np.diag([1, 1j]))], 2)
+    assert plan.blocks()[0]["diag"]

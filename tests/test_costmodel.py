@@ -34,10 +34,10 @@ def C(P):
 
 
 def test_features(C):
-    f = C.features(30, [29, 3, 0], monomial=False)
+    f = C.features(30, [29, 3, 0], diagonal=False)
     np.testing.assert_allclose(f, [30 / 35, 3 / 8, 0, 3 / 35, 29 / 35, -0.25, -0.25, -0.25, -0.25, 0], rtol=1e-6)
-    g = C.features(12, [5, 6], monomial=True)
-    assert abs(g[9] - 0.75) < 1e-7
+    g = C.features(12, [5, 6], diagonal=True)
+    assert g[9] == 1.0
 
 
 def test_host_forward_matches_oracle(C):
@@ -163,3 +163,22 @@ def test_learned_planner_search_prefers_cheaper_plan(P, C):
     for cap in (4, 5, 6, 7):
         assert best <= predicted(P.Plan.dp(n, gates, cap, cap, 64, params=params, reorder=True)) + 1e-9
     assert best < predicted(P.Plan.greedy(n, gates, 5))
+
+
+def test_repeated_rounds_exact_and_never_worse(P, C):
+    """Reorder-and-fuse repeated on the blocks: same state, no more blocks, no higher score."""
+    n = 10
+    gates = W.brickwork(n, 5, 3) + W.qft(n)
+    ref = oracle.run(n, gates)
+    once = P.Plan.dp(n, gates, 4, 4, 16, reorder=True)
+    again = P.Plan.dp(n, gates, 4, 4, 16, reorder=True, repeat=True)
+    assert len(again) <= len(once)
+    assert sum(paper_score(b) for b in again.blocks()) <= sum(paper_score(b) for b in once.blocks())
+    for plan in (again, P.Plan.paper(n, gates), P.Plan.learned(n, gates, C.init_params(6))):
+        psi = oracle.zero_state(n)
+        for b in plan.blocks():
+            assert b["k"] <= 7
+            oracle.apply_gate(psi, b["matrix"], b["targets"])
+        m = oracle.metrics(ref, psi)
+        assert m["infidelity"] < 1e-12 and m["max_abs"] < 1e-12
+        assert sum(b["n_gates"] for b in plan.blocks()) == len(gates)

@@ -139,6 +139,55 @@ def test_auto_selector_mixed_widths(P):
     assert st["by_variant"][P._native.VARIANT["mfma"]] >= 4
 
 
+def random_diagonal(n, k, rng, targets=None):
+    t = tuple(int(q) for q in (targets if targets is not None else rng.choice(n, k, replace=False)))
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << k))
+    return W.Gate("diag%d" % k, t, np.diag(ph), diag=True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 9, 17])
+def test_diagonal_lowering_matches_oracle(P, n):
+    """Exactly diagonal matrices take the streaming diagonal kernel (any k <= 8, any target order)."""
+    rng = np.random.default_rng(40 + n)
+    gates = rand_state_gates(n, rng, 1)
+    diag_gates = []
+    for k in range(1, min(n, 8) + 1):
+        diag_gates.append(random_diagonal(n, k, rng))
+    diag_gates.append(random_diagonal(n, 1, rng, [0]))
+    diag_gates.append(random_diagonal(n, 1, rng, [n - 1]))
+    if n >= 3:
+        diag_gates.append(random_diagonal(n, 3, rng, [n - 1, 0, n // 2]))
+    gates += diag_gates
+    ref = oracle.run(n, gates)
+    sv = P.StateVector(n)
+    sv.apply_gates(gates[:-len(diag_gates)])
+    before = sv.stats()["by_variant"][P._native.VARIANT["diag"]]
+    sv.apply_gates(diag_gates)
+    after = sv.stats()["by_variant"][P._native.VARIANT["diag"]]
+    assert after - before == len(diag_gates)
+    check_close(ref, gpu_logical(sv), what="diag n=%d" % n)
+    sv.close()
+
+
+def test_diagonal_forced_and_rejected(P):
+    n = 12
+    rng = np.random.default_rng(3)
+    sv = P.StateVector(n)
+    sv.set_variant("diag")
+    with pytest.raises(RuntimeError):
+        sv.apply(W.random_dense(n, 2, rng).matrix, [1, 2])
+    # a diagonal gate forced through the dense MFMA sweep gives the same state
+    g = random_diagonal(n, 5, rng, [0, 3, 4, 8, 11])
+    prep = rand_state_gates(n, rng, 1)
+    ref = oracle.run(n, prep + [g])
+    sv.set_variant("auto")
+    sv.apply_gates(prep)
+    sv.set_variant("mfma")
+    sv.apply(g.matrix, g.targets)
+    check_close(ref, gpu_logical(sv), what="diag via mfma")
+    sv.close()
+
+
 # ---------------------------------------------------------------- whole circuits
 def test_c1_gate_by_gate_n20_and_samples(P):
     """N=20, 20 brickwork layers applied gate by gate; 10^4 samples, fixed seed."""
