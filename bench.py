@@ -289,30 +289,32 @@ def bench_learned(args):
     P.Plan.greedy(n, gates[:200], 5).run(sv)
     P.Plan.learned(n, gates[:200], params).run(sv)
     sync()
+    planners = {"greedy": lambda c: P.Plan.greedy(n, c, args.kmax),
+                "learned": lambda c: P.Plan.learned(n, c, params),
+                "paper": lambda c: P.Plan.paper(n, c)}
     res = {}
-    for name in ("greedy", "learned"):
+    for name in ("greedy", "learned", "paper"):
         t0 = time.perf_counter()
-        if name == "greedy":
-            fwd = P.Plan.greedy(n, gates, args.kmax)
-            bwd = P.Plan.greedy(n, inv, args.kmax)
-        else:
-            fwd = P.Plan.learned(n, gates, params)
-            bwd = P.Plan.learned(n, inv, params)
-        plan_s = (time.perf_counter() - t0) / 2
+        fwd = planners[name](gates)
+        plan_s = time.perf_counter() - t0
         sv.reset()
         ex = _timed(lambda: fwd.run(sv), sync)
         log("bench learned: %s %d blocks, execute %.3f s" % (name, len(fwd), ex))
+        ks = {}
+        for b in fwd.blocks():
+            ks[str(b["k"])] = ks.get(str(b["k"]), 0) + 1
+        res[name] = {"blocks": len(fwd), "diag_blocks": sum(1 for b in fwd.blocks() if b["diag"]),
+                     "blocks_by_k": ks, "plan_s": plan_s, "execute_s": ex, "end_to_end_s": plan_s + ex}
+        if name == "paper":  # context only: no echo (another ~900 sweeps)
+            continue
+        bwd = planners[name](inv)
         bwd.run(sv)
         sv.sync()
         a0 = sv.amps[0].item()
         nrm = sv.norm()
-        echo = abs(a0) ** 2 / nrm  # overlap of normalized states
-        ks = {}
-        for b in fwd.blocks():
-            ks[str(b["k"])] = ks.get(str(b["k"]), 0) + 1
-        res[name] = {"blocks": len(fwd), "blocks_by_k": ks, "plan_s": plan_s, "execute_s": ex,
-                     "end_to_end_s": plan_s + ex, "echo_fidelity": echo, "norm_minus_1": nrm - 1, "layout_identity":
-                     bool(np.array_equal(sv.layout(), np.arange(n)))}
+        res[name].update({"echo_fidelity": abs(a0) ** 2 / nrm,  # overlap of normalized states
+                          "norm_minus_1": nrm - 1,
+                          "layout_identity": bool(np.array_equal(sv.layout(), np.arange(n)))})
     sv.close()
     g, l = res["greedy"], res["learned"]
 
@@ -323,19 +325,18 @@ def bench_learned(args):
             tot += float(np.exp(C.forward_host(params, f[None])[0] + (n - 30) * np.log(2.0)))
         return tot / 1e3
 
-    paper = P.Plan.dp(n, gates, 5, 5, 64, reorder=True)  # the method without the network: 4^k score
     out = {
         "metric": "learned vs greedy fusion: end-to-end time (plan + execute), N=%d c64 depth %d" % (n, depth),
         "value": g["end_to_end_s"] / l["end_to_end_s"], "unit": "x speedup (greedy time / learned time)",
         "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "N=%d complex64 brickwork depth %d (seed %d); greedy k<=%d (circuit order) vs "
-                               "learned planner (commute-aware reorder + DP on predicted sweep times, cap chosen "
-                               "by the model among 4..7, window 64)" % (n, depth, args.seed, args.kmax),
+                               "learned planner (commute-aware reorder + DP on predicted sweep times, dense cap "
+                               "chosen by the model among 4..7, up to four rounds, window 64)"
+                               % (n, depth, args.seed, args.kmax),
                    "gates": len(gates)},
         "greedy": g, "learned": l,
-        "predicted_s": {"greedy": predicted(P.Plan.greedy(n, gates, args.kmax)),
-                        "learned": predicted(P.Plan.learned(n, gates, params)),
-                        "paper_score_dp_with_reorder": predicted(paper), "paper_score_dp_blocks": len(paper)},
+        "paper_pipeline": res["paper"],  # 4^k / 1 score, reorder, DP, merge, <= 4 rounds; caps 6 / 6
+        "predicted_s": {name: predicted(planners[name](gates)) for name in planners},
         "execute_gain": 1 - l["execute_s"] / g["execute_s"],
         "cost_model": {k: meta.get(k) for k in ("rows", "rmse_log_ms_train", "rmse_log_ms_test", "n_values")},
     }

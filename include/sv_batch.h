@@ -12,7 +12,9 @@
  * qubits, angles free) are grouped into packs of P that one workgroup runs in
  * lockstep; P per qubit count comes from sv_batch_autotune or the caller.
  * States of at most 2^14 amplitudes per pack slice stay in LDS for the whole
- * circuit; larger states are updated in the caller's state buffer.
+ * circuit.  Larger states live in the caller's state buffer and run as
+ * passes: each pass streams every 2^14-amplitude slice of a chosen set of 14
+ * qubits through LDS and applies there every gate that acts only on them.
  * Workgroups take packs from an atomic queue ordered by decreasing cost and
  * exit when the queue is empty.
  */

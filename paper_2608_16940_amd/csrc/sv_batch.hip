@@ -2,9 +2,13 @@
 // launch.  Each workgroup (512 threads) takes packs from an atomic queue; a
 // pack is P circuits with the same qubit count and gate structure, run in
 // lockstep by 512/P threads each.  States of up to 2^14 amplitudes per slice
-// live in LDS from |0...0> to the final write-back; larger states are updated
-// in place in the caller's buffer, which stays L2/MALL-resident (<= 2 MiB).
+// live in LDS from |0...0> to the final write-back.  Larger states run as
+// passes: a pass names the 14 qubits a 2^14-amplitude LDS slice holds and the
+// gates that act only on them; every slice of the state is gathered into LDS,
+// gets all of the pass's gates, and is written back (one read and one write
+// of the state per pass instead of one per gate).
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <string>
@@ -46,6 +50,37 @@ __device__ __forceinline__ float2 cmad(float ar, float ai, float2 x, float2 acc)
   return acc;
 }
 
+constexpr int kSliceBits = 14;
+constexpr int kGatePass = 2;  // internal record: q0 = slice qubit mask, q1 = gates in the pass
+
+// One gate on a state of `dim` amplitudes at st (LDS or global), threads lt of Tc.
+__device__ __forceinline__ void apply_gate(const BGate &G, float2 *st, int64_t dim, int lt, int Tc) {
+  if (G.kind == SV_BATCH_GATE_1Q) {
+    const int q = G.q0;
+    for (int64_t p = lt; p < dim / 2; p += Tc) {
+      const int64_t x = ins0(p, q), y = x | (int64_t(1) << q);
+      const float2 a = st[x], b = st[y];
+      float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
+      o0 = cmad(G.m[0], G.m[1], a, o0);
+      o0 = cmad(G.m[2], G.m[3], b, o0);
+      o1 = cmad(G.m[4], G.m[5], a, o1);
+      o1 = cmad(G.m[6], G.m[7], b, o1);
+      st[x] = o0;
+      st[y] = o1;
+    }
+  } else if (G.kind == SV_BATCH_GATE_CNOT) {
+    const int cq = G.q0, tq = G.q1;
+    const int lo = cq < tq ? cq : tq, hi = cq < tq ? tq : cq;
+    for (int64_t p = lt; p < dim / 4; p += Tc) {
+      const int64_t x = ins0(ins0(p, lo), hi) | (int64_t(1) << cq);
+      const int64_t y = x | (int64_t(1) << tq);
+      const float2 a = st[x];
+      st[x] = st[y];
+      st[y] = a;
+    }
+  }
+}
+
 __global__ void k_batch_reset(unsigned *counter) {
   if (threadIdx.x == 0) *counter = 0u;
 }
@@ -55,6 +90,7 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
                                                double *__restrict__ z0, unsigned *__restrict__ counter) {
   __shared__ float2 lds[kLdsAmps];
   __shared__ double red[kBT];
+  __shared__ int32_t offlo[128], offhi[128];  // slice index -> state offset, low and high 7 bits
   __shared__ int item_s;
   const int tid = threadIdx.x;
   while (true) {
@@ -75,36 +111,55 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
 
     for (int64_t x = lt; x < dim; x += Tc) st[x] = make_float2(x == 0 ? 1.f : 0.f, 0.f);
     __syncthreads();
-    // lockstep over the pack: a circuit past its last gate only meets the barriers
-    for (int g = 0; g < ngates; ++g) {
-      BGate G;
-      G.kind = -1;
-      if (g < my_ng) G = gl[g];
-      if (G.kind == SV_BATCH_GATE_1Q) {
-        const int q = G.q0;
-        for (int64_t p = lt; p < dim / 2; p += Tc) {
-          const int64_t x = ins0(p, q), y = x | (int64_t(1) << q);
-          const float2 a = st[x], b = st[y];
-          float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
-          o0 = cmad(G.m[0], G.m[1], a, o0);
-          o0 = cmad(G.m[2], G.m[3], b, o0);
-          o1 = cmad(G.m[4], G.m[5], a, o1);
-          o1 = cmad(G.m[6], G.m[7], b, o1);
-          st[x] = o0;
-          st[y] = o1;
-        }
-      } else if (G.kind == SV_BATCH_GATE_CNOT) {
-        const int cq = G.q0, tq = G.q1;
-        const int lo = cq < tq ? cq : tq, hi = cq < tq ? tq : cq;
-        for (int64_t p = lt; p < dim / 4; p += Tc) {
-          const int64_t x = ins0(ins0(p, lo), hi) | (int64_t(1) << cq);
-          const int64_t y = x | (int64_t(1) << tq);
-          const float2 a = st[x];
-          st[x] = st[y];
-          st[y] = a;
-        }
+    if (in_lds) {
+      // lockstep over the pack: a circuit past its last gate only meets the barriers
+      for (int g = 0; g < ngates; ++g) {
+        BGate G;
+        G.kind = -1;
+        if (g < my_ng) G = gl[g];
+        apply_gate(G, st, dim, lt, Tc);
+        __syncthreads();
       }
-      __syncthreads();
+    } else {
+      // P = 1: the whole workgroup runs the passes of one circuit
+      for (int g = 0; g < my_ng;) {
+        const BGate M = gl[g];  // pass record
+        const uint32_t mask = uint32_t(M.q0);
+        const int cnt = M.q1;
+        if (tid < 256) {
+          // slice bit j (j = 0..13) is the j-th lowest qubit of the mask
+          const int half = tid >> 7, v = tid & 127;
+          int32_t off = 0;
+          int j = 0;
+          for (int q = 0; q < n; ++q) {
+            if (!((mask >> q) & 1u)) continue;
+            const int jj = j - 7 * half;
+            if (jj >= 0 && jj < 7 && ((v >> jj) & 1)) off |= int32_t(1) << q;
+            ++j;
+          }
+          (half ? offhi : offlo)[v] = off;
+        }
+        __syncthreads();
+        const int nsl = 1 << (n - kSliceBits);
+        for (int sl = 0; sl < nsl; ++sl) {
+          int64_t base = 0;
+          int r = 0;
+          for (int q = 0; q < n; ++q) {
+            if ((mask >> q) & 1u) continue;
+            if ((sl >> r) & 1) base |= int64_t(1) << q;
+            ++r;
+          }
+          for (int x = tid; x < kLdsAmps; x += kBT) lds[x] = st[base + offlo[x & 127] + offhi[x >> 7]];
+          __syncthreads();
+          for (int j = 1; j <= cnt; ++j) {
+            apply_gate(gl[g + j], lds, kLdsAmps, tid, kBT);
+            __syncthreads();
+          }
+          for (int x = tid; x < kLdsAmps; x += kBT) st[base + offlo[x & 127] + offhi[x >> 7]] = lds[x];
+          __syncthreads();
+        }
+        g += 1 + cnt;
+      }
     }
     // <Z_0> in FP64 over this circuit's slice
     double s = 0.0;
@@ -133,6 +188,85 @@ struct Packed {
   std::vector<BItem> items;
   int ncirc = 0;
 };
+
+// Rewrite the gate list of a circuit with more than 2^14 amplitudes as
+// passes (a pass record, then its gates with qubits renumbered to slice bit
+// positions).  A gate joins the current pass when it is ready (every earlier
+// gate on its qubits applied) and all its qubits are in the pass's slice;
+// ready gates of one moment act on disjoint qubits, so any order among them
+// is exact.  When none is left, the next slice keeps qubits 0..2 (runs of 8
+// contiguous amplitudes), the qubits of the earliest ready gate, then the
+// qubits whose next gate comes soonest: the farthest next use stays out
+// (Corollary 1), ties to the lower qubit.
+std::vector<BGate> make_passes(const std::vector<BGate> &g, int n) {
+  std::vector<std::vector<int>> per_q(static_cast<size_t>(n));
+  for (int i = 0; i < int(g.size()); ++i) {
+    per_q[size_t(g[size_t(i)].q0)].push_back(i);
+    if (g[size_t(i)].kind == SV_BATCH_GATE_CNOT) per_q[size_t(g[size_t(i)].q1)].push_back(i);
+  }
+  std::vector<size_t> head(static_cast<size_t>(n), 0);
+  auto head_gate = [&](int q) {
+    return head[size_t(q)] < per_q[size_t(q)].size() ? per_q[size_t(q)][head[size_t(q)]] : INT_MAX;
+  };
+  auto qubits_of = [&](const BGate &b) {
+    uint32_t m = 1u << b.q0;
+    if (b.kind == SV_BATCH_GATE_CNOT) m |= 1u << b.q1;
+    return m;
+  };
+  auto ready = [&](int i) {
+    const BGate &b = g[size_t(i)];
+    return head_gate(b.q0) == i && (b.kind != SV_BATCH_GATE_CNOT || head_gate(b.q1) == i);
+  };
+  uint32_t mask = (1u << kSliceBits) - 1;
+  std::vector<BGate> out;
+  size_t left = g.size();
+  while (left > 0) {
+    std::vector<BGate> pass;
+    for (bool progress = true; progress;) {
+      progress = false;
+      for (int q = 0; q < n; ++q) {
+        const int i = head_gate(q);
+        if (i == INT_MAX || !ready(i)) continue;
+        const BGate &b = g[size_t(i)];
+        if (qubits_of(b) & ~mask) continue;
+        BGate l = b;
+        l.q0 = __builtin_popcount(mask & ((1u << b.q0) - 1));
+        if (b.kind == SV_BATCH_GATE_CNOT) l.q1 = __builtin_popcount(mask & ((1u << b.q1) - 1));
+        pass.push_back(l);
+        ++head[size_t(b.q0)];
+        if (b.kind == SV_BATCH_GATE_CNOT) ++head[size_t(b.q1)];
+        --left;
+        progress = true;
+      }
+    }
+    if (!pass.empty()) {
+      BGate rec;
+      std::memset(&rec, 0, sizeof(rec));
+      rec.kind = kGatePass;
+      rec.q0 = int32_t(mask);
+      rec.q1 = int32_t(pass.size());
+      out.push_back(rec);
+      out.insert(out.end(), pass.begin(), pass.end());
+    }
+    if (left == 0) break;
+    int first = INT_MAX;
+    for (int q = 0; q < n; ++q) {
+      const int i = head_gate(q);
+      if (i != INT_MAX && ready(i)) first = std::min(first, i);
+    }
+    uint32_t m = 0x7u | qubits_of(g[size_t(first)]);
+    std::vector<int> rest;
+    for (int q = 0; q < n; ++q)
+      if (!((m >> q) & 1u)) rest.push_back(q);
+    std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return head_gate(a) < head_gate(b); });
+    for (int q : rest) {
+      if (__builtin_popcount(m) >= kSliceBits) break;
+      m |= 1u << q;
+    }
+    mask = m;
+  }
+  return out;
+}
 
 bool valid_config(const int32_t *cfg) {
   for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
@@ -229,6 +363,7 @@ int pack_batch(int count, const sv_batch_circuit *circs, size_t states_bytes, co
       }
     }
     flush();
+    if (C.n_qubits > kSliceBits) g = make_passes(g, C.n_qubits);
     groups[C.n_qubits].push_back(i);
   }
   out->ncirc = count;
@@ -330,8 +465,8 @@ extern "C" {
 
 size_t sv_batch_workspace_bytes(int count, const sv_batch_circuit *circs) {
   if (count < 0 || (count > 0 && !circs)) return 0;
-  size_t ng = 0;
-  for (int i = 0; i < count; ++i) ng += size_t(std::max(0, circs[i].n_gates));
+  size_t ng = 0;  // at most one pass record per gate on top of the gates
+  for (int i = 0; i < count; ++i) ng += 2 * size_t(std::max(0, circs[i].n_gates));
   return 256 + align256(sizeof(double) * size_t(std::max(1, count))) +
          align256(sizeof(BItem) * size_t(std::max(1, count))) + align256(sizeof(BGate) * std::max<size_t>(1, ng));
 }

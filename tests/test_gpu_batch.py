@@ -35,6 +35,32 @@ def test_batch_matches_oracle_every_circuit(B):
     print("batch worst max|d|", worst, flush=True)
 
 
+def test_batch_multi_pass_states(B):
+    """States above 2^14 amplitudes run as LDS slice passes; reversed ladders and
+    long-range CNOTs force many passes with changing slice qubit sets."""
+    rng = np.random.default_rng(77)
+    circs = []
+    for n in (15, 16, 17, 18):
+        gates = []
+        for layer in range(5):
+            for q in rng.permutation(n):
+                gates.append(W.Gate("ry", (int(q),), W.ry(float(rng.uniform(0, 2 * np.pi)))))
+            order = range(n - 2, -1, -1) if layer % 2 else range(n - 1)
+            for q in order:
+                gates.append(W.Gate("cnot", (q + 1, q) if layer % 2 else (q, q + 1), W.cnot()))
+            gates.append(W.Gate("cnot", (0, n - 1), W.cnot()))
+            gates.append(W.Gate("cnot", (n - 1, 3), W.cnot()))
+            gates.append(W.Gate("rz", (n - 1,), W.rz(float(rng.uniform(0, 2 * np.pi)))))
+        circs.append((n, gates))
+    b = B.Batch(circs).allocate()
+    z0 = b.run()
+    for i, (n, gates) in enumerate(circs):
+        ref = oracle.run(n, gates)
+        m = oracle.metrics(ref, b.state(i))
+        assert m["infidelity"] <= 1e-5 and m["max_abs"] <= 1e-5 and m["rel_l2"] <= 1e-5, (n, m)
+        assert abs(z0[i] - oracle.expect_z(ref, 0)) <= 1e-5
+
+
 def test_batch_configs_agree_and_autotune(B):
     circs = W.batch_family(64, seed=9, n_lo=10, n_hi=14, d_lo=6, d_hi=6)
     b = B.Batch(circs).allocate()
