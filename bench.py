@@ -95,10 +95,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one plain device copy of the state's size "
                          "(reference dispatch for scaling HBM byte counters)")
-    ap.add_argument("--workload", default="headline", choices=["headline", "learned", "batch", "precision"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "learned", "batch", "precision", "c1"],
                     help="headline (default): N=30 brickwork+QFT, greedy k<=5; learned: learned-DP vs greedy "
-                         "plans at N=34 depth 20; batch: 4096 small circuits in one launch; precision: k=6/7 "
-                         "FP32 vs BF16x3 sweeps at N=32")
+                         "plans at N=34 depth 20; batch: 4096 small circuits in one launch; precision: N=32 "
+                         "depth-16 circuit fused to k<=6/7, FP32 vs BF16x3; c1: N=20 gate by gate + 10^4 shots")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -119,6 +120,8 @@ def main():
         return bench_batch(args)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "c1":
+        return bench_c1(args)
 
     n = args.n
     gates = W.headline(n, args.depth, args.seed)
@@ -382,7 +385,7 @@ def bench_batch(args):
 
 
 def bench_precision(args):
-    """k=6 and k=7 fused sweeps at N=32 (32 GiB): FP32 MFMA (Gauss) vs BF16x3 MFMA."""
+    """Depth-16 brickwork at N=32 (32 GiB) fused to k<=6 and k<=7: FP32 MFMA (Gauss) vs BF16x3 MFMA."""
     import numpy as np
     import torch
 
@@ -390,7 +393,47 @@ def bench_precision(args):
     import workloads as W
 
     n = args.n if args.n != 30 else 32
+    depth = 16
+    gates = W.brickwork(n, depth, args.seed)
     sv = P.StateVector(n, device="cuda:0")
+    sweep = 16.0 * (1 << n)
+    peak = {"fp32": 157.3, "bf16x3": 2500.0}  # dense TFLOP/s of the MFMA units used
+    circuits = {}
+    for kcap in (6, 7):
+        plan = P.Plan.greedy(n, gates, kcap)
+        blocks = plan.blocks()
+        dense = [b for b in blocks if not b["diag"]]
+        alg = sum(8.0 * (1 << b["k"]) for b in dense) * (1 << n)  # complex MACs as 8 real flops
+        for prec in ("fp32", "bf16x3"):
+            sv.set_precision(prec)
+            sv.reset()
+            plan.run(sv)
+            sv.sync()
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                sv.reset()
+                plan.run(sv)
+            sv.sync()
+            s_run = (time.perf_counter() - t0) / reps
+            # executed MFMA work: Gauss form 6 * 2^k per amplitude (k >= 5, FP32), embedding 8 * 2^k
+            # (FP32 k = 4), three bf16 embeddings 24 * 2^k (BF16x3)
+            ex = 0.0
+            for b in dense:
+                if b["k"] < 4:
+                    continue
+                f = 24.0 if prec == "bf16x3" else (6.0 if b["k"] >= 5 else 8.0)
+                ex += f * (1 << b["k"]) * (1 << n)
+            kb = {}
+            for b in blocks:
+                kb[str(b["k"])] = kb.get(str(b["k"]), 0) + 1
+            circuits["k%d_%s" % (kcap, prec)] = {
+                "s_per_circuit": s_run, "blocks": len(blocks), "blocks_by_k": kb,
+                "GBps_per_sweep": len(blocks) * sweep / s_run / 1e9,
+                "alg_TFLOPs": alg / s_run / 1e12, "mfma_TFLOPs": ex / s_run / 1e12,
+                "mfma_frac_of_peak": ex / s_run / 1e12 / peak[prec]}
+            log("bench precision: k<=%d %s %.3f s per circuit (%d blocks)" % (kcap, prec, s_run, len(blocks)))
+    # single sweeps of random dense gates on random targets
     rng = np.random.default_rng(args.seed)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows = {}
@@ -406,17 +449,64 @@ def bench_precision(args):
             ev1.record()
             ev1.synchronize()
             ms = ev0.elapsed_time(ev1) / reps
-            sweep = 16.0 * (1 << n)
-            flops = 8.0 * (1 << k) * (1 << n)  # complex multiply-adds as 8 real flops
-            rows["k%d_%s" % (k, prec)] = {"ms": ms, "GBps": sweep / ms / 1e6, "TFLOPs": flops / ms / 1e9}
-            log("bench precision: k=%d %s %.3f ms" % (k, prec, ms))
+            f = 24.0 if prec == "bf16x3" else 6.0
+            ex = f * (1 << k) * (1 << n)
+            rows["k%d_%s" % (k, prec)] = {"ms": ms, "GBps": sweep / ms / 1e6,
+                                          "alg_TFLOPs": 8.0 * (1 << k) * (1 << n) / ms / 1e9,
+                                          "mfma_frac_of_peak": ex / ms / 1e9 / peak[prec]}
+    sv.close()
+    k7 = rows["k7_fp32"]
+    out = {
+        "metric": "N=%d depth-%d circuit fused to k<=6 / k<=7: FP32 MFMA vs BF16x3 MFMA" % (n, depth),
+        "value": circuits["k7_bf16x3"]["s_per_circuit"], "unit": "s per circuit (k<=7, BF16x3)",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "fp32 / bf16x3 (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": "brickwork depth %d (Haar SU(2) + CZ, seed %d), N=%d complex64, greedy fusion"
+                               % (depth, args.seed, n)},
+        "circuits": circuits, "single_sweeps": rows,
+        "roofline": {"bound": "mfma", "kernel": "k_tile_mfma<K=7> fp32 (Gauss)",
+                     "achieved": k7["mfma_frac_of_peak"] * peak["fp32"], "peak": peak["fp32"],
+                     "unit": "TFLOP/s", "frac": k7["mfma_frac_of_peak"], "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_c1(args):
+    """N=20 brickwork, 20 layers, gate by gate (no fusion), then 10^4 samples: launch-bound."""
+    import paper_2608_16940_amd as P
+    import workloads as W
+
+    n = args.n if args.n != 30 else 20
+    gates = W.brickwork(n, 20, args.seed)
+    plan = P.Plan.greedy(n, gates, 1)  # width cap 1: every gate of this circuit stays a singleton
+    assert len(plan) == len(gates)
+    sv = P.StateVector(n, device="cuda:0")
+    shots = 10000
+    for _ in range(max(1, args.warmup)):
+        sv.reset()
+        plan.run(sv)
+        sv.sample(0x5EED, shots)
+    sv.sync()
+    reps = max(1, args.steps) * 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sv.reset()
+        plan.run(sv)
+    sv.sync()
+    t_gates = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sv.sample(0x5EED, shots)
+    t_sample = (time.perf_counter() - t0) / reps
+    st = sv.stats()
     sv.close()
     out = {
-        "metric": "fused k-qubit sweep time at N=%d, FP32 MFMA vs BF16x3 MFMA" % n,
-        "value": rows["k7_bf16x3"]["GBps"], "unit": "GB/s (k=7, BF16x3)", "n_gpus": 1, "higher_is_better": True,
-        "dtype": "fp32 / bf16x3 (fp32 accumulate)", "data": "synthetic",
-        "config": {"workload": "random dense k-qubit unitaries on random targets, N=%d complex64" % n},
-        "sweeps": rows,
+        "metric": "gate-by-gate applies per second, N=%d c64 (cache-resident)" % n,
+        "value": len(gates) / t_gates, "unit": "gates/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "N=%d brickwork 20 layers (Haar SU(2) + CZ, seed %d), no fusion; %d shots"
+                               % (n, args.seed, shots), "gates": len(gates)},
+        "us_per_gate": t_gates / len(gates) * 1e6, "ms_per_circuit": t_gates * 1e3,
+        "ms_per_10k_samples": t_sample * 1e3, "by_variant_last": st["by_variant"],
     }
     print(json.dumps(out), flush=True)
 

@@ -221,11 +221,15 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
       std::vector<float2> d(static_cast<size_t>(D));
       for (int r = 0; r < D; ++r)
         d[r] = make_float2(float(matrix[2 * (r * D + r)]), float(matrix[2 * (r * D + r) + 1]));
+      if (k <= 4) {  // small tables ride in the kernel arguments: no staging copy
+        e = launch_diag(s->amps, n, k, A, nullptr, d.data(), s->st);
+        break;
+      }
       void *dev = nullptr;
       int slot = 0;
       int rc = stage(s, d.data(), d.size() * sizeof(float2), &dev, &slot);
       if (rc) return rc;
-      e = launch_diag(s->amps, n, k, A, static_cast<const float2 *>(dev), s->st);
+      e = launch_diag(s->amps, n, k, A, static_cast<const float2 *>(dev), nullptr, s->st);
       if (e == hipSuccess) {
         rc = release_slot(s, slot);
         if (rc) return rc;

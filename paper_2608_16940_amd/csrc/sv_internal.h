@@ -63,8 +63,10 @@ hipError_t launch_dense_valu(float2 *psi, int n, int k, const int32_t *phys_targ
 hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStream_t st);
 
 // any k <= 8; m_dev: device complex64 row-major matrix.
-// Diagonal operator: d_dev holds the 2^k diagonal entries (device complex64).
-hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *phys_targets, const float2 *d_dev, hipStream_t st);
+// Diagonal operator: the 2^k diagonal entries (complex64) in device memory
+// (d_dev), or for k <= 4 from the host by value (d_dev null, d_host set).
+hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *phys_targets, const float2 *d_dev,
+                       const float2 *d_host, hipStream_t st);
 hipError_t launch_dense_generic(float2 *psi, int n, int k, const int32_t *phys_targets, const float2 *m_dev,
                                 hipStream_t st);
 

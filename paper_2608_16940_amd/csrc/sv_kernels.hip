@@ -138,17 +138,19 @@ __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ ps
 // chunk per thread over a full grid streams fastest on MI355X (6.1 TB/s in
 // place at N=30, against 5.5 TB/s for four chunks per thread on a capped,
 // grid-strided launch).
+constexpr int kDiagByValue = 16;  // tables up to k = 4 travel in the kernel arguments
 struct DiagArgs {
   int k;
   int tgt[8];  // physical position of block bit j
   int bit0;    // r-bit set by physical bit 0 (0 if bit 0 is not a target)
+  float2 small[kDiagByValue];  // the table when dtab is null
 };
 
 template <int UNR>
 __global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, int64_t nchunks,
                                                    const float2 *__restrict__ dtab, DiagArgs a) {
   __shared__ float2 tab[256];
-  for (int i = threadIdx.x; i < (1 << a.k); i += kThreads) tab[i] = dtab[i];
+  for (int i = threadIdx.x; i < (1 << a.k); i += kThreads) tab[i] = dtab ? dtab[i] : a.small[i];
   __syncthreads();
   const int64_t step = int64_t(gridDim.x) * kThreads * UNR;
   for (int64_t c0 = int64_t(blockIdx.x) * kThreads * UNR + threadIdx.x; c0 < nchunks; c0 += step) {
@@ -515,11 +517,14 @@ hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2 *d_dev, hipStream_t st) {
-  if (k < 1 || k > 8 || k > n) return hipErrorInvalidValue;
+hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2 *d_dev, const float2 *d_host,
+                       hipStream_t st) {
+  if (k < 1 || k > 8 || k > n || (!d_dev && (!d_host || k > 4))) return hipErrorInvalidValue;
   DiagArgs a;
   std::memset(&a, 0, sizeof(a));
   a.k = k;
+  if (!d_dev)
+    for (int i = 0; i < (1 << k); ++i) a.small[i] = d_host[i];
   for (int j = 0; j < k; ++j) {
     a.tgt[j] = A[j];
     if (A[j] == 0) a.bit0 = 1 << j;
