@@ -27,29 +27,50 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_tile_mfma_k5_n30.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2608_16940_amd", "csrc", "sv_tile.hip")
+CSRC = os.path.join(ROOT, "paper_2608_16940_amd", "csrc")
+# committed rocprofv3 byte counters per kernel class: (summary json, kernel source file)
+PMC_FILES = {
+    "k_tile_mfma<K=5> fp32": ("pmc_traffic_tile_mfma_k5_n30.json", "sv_tile.hip"),
+    "k_diag": ("pmc_traffic_diag_n30.json", "sv_kernels.hip"),
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
+def source_sha(name: str) -> str:
+    with open(os.path.join(CSRC, name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def pmc_traffic():
-    """HBM bytes per launch of the dominant kernel from committed rocprofv3 counters, if current."""
+def pmc_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from committed rocprofv3 counters, if its source is unchanged."""
+    if kernel not in PMC_FILES:
+        return None
+    path, src = PMC_FILES[kernel]
     try:
-        with open(PMC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", path)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_sha") != kernel_sha():
+    if d.get("source_sha") != source_sha(src):
         return None
     return d.get("bytes_per_launch")
+
+
+def kernel_class(b, n):
+    """The lowering sv_apply_fused picks for a block (its automatic selector)."""
+    if b["diag"]:
+        return "k_diag"
+    k = b["k"]
+    if k == 1 and b["targets"][0] <= 6:
+        return "k_1q_shuffle"
+    if 4 <= k <= 7:
+        return "k_tile_mfma<K=%d> fp32" % k
+    if k <= 4:
+        return "k_dense_valu<%d>" % k
+    return "k_dense_generic"
 
 
 def cpu_baseline(n, gates, n_blocks, seconds):
@@ -133,26 +154,23 @@ def main():
     kcount = {}
     for b in blocks:
         kcount[b["k"]] = kcount.get(b["k"], 0) + 1
-    kdom = max(kcount, key=lambda k: (kcount[k], k))
+    classes = [kernel_class(b, n) for b in blocks]
     log("bench: n=%d gates=%d blocks=%d by_k=%s plan_s=%.2f" % (n, len(gates), nb, kcount, plan_s))
 
     sv = P.StateVector(n, device="cuda:0")
-    stream = torch.cuda.current_stream()
-    ndom = kcount[kdom]
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(ndom * args.steps)]
-    dom_times = []
+    stream = torch.cuda.current_stream()  # the library launches on this stream
+    # HIP events around every sweep of every timed step (per-kernel averages)
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in blocks]
+          for _ in range(args.steps)]
 
     def step(timed_index):
         sv.reset()
-        j = 0
-        for b in blocks:
-            if timed_index is not None and b["k"] == kdom:
-                e0, e1 = ev[timed_index * ndom + j]
+        for j, b in enumerate(blocks):
+            if timed_index is not None:
+                e0, e1 = ev[timed_index][j]
                 e0.record(stream)
                 sv.apply(b["matrix"], b["targets"])
                 e1.record(stream)
-                j += 1
             else:
                 sv.apply(b["matrix"], b["targets"])
         return sv.sample(0x5EED, args.shots)
@@ -167,16 +185,24 @@ def main():
         step(s)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    for e0, e1 in ev:
-        dom_times.append(e0.elapsed_time(e1) / 1e3)
+    per_class = {}
+    for s in range(args.steps):
+        for j, c in enumerate(classes):
+            e0, e1 = ev[s][j]
+            per_class.setdefault(c, []).append(e0.elapsed_time(e1) / 1e3)
     log("bench: timed %d steps in %.3f s" % (args.steps, el))
 
     ms_per_step = el / args.steps * 1e3
     value = nb * args.steps / el
     sweep_bytes = 16.0 * (1 << n)
-    dom_avg = float(np.mean(dom_times))
-    achieved = sweep_bytes / dom_avg / 1e9
-    traffic = pmc_traffic()
+    kernels = {}
+    for c, ts in per_class.items():
+        avg = float(np.mean(ts))
+        kernels[c] = {"launches": len(ts), "avg_ms": avg * 1e3, "total_ms_per_step": float(np.sum(ts)) * 1e3 / args.steps,
+                      "GBps": sweep_bytes / avg / 1e9, "frac": sweep_bytes / avg / 1e9 / HBM_PEAK_GBS}
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms_per_step"])
+    achieved = kernels[dom]["GBps"]
+    traffic = pmc_traffic(dom)
     st = sv.stats()
 
     def step_time(plan, reps, prec="fp32"):
@@ -247,16 +273,17 @@ def main():
         "effective_gbps_per_step": value * sweep_bytes / 1e9,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_tile_mfma<K=%d> fp32" % kdom,
+            "kernel": dom,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "launches": len(dom_times),
-            "avg_ms": dom_avg * 1e3,
+            "launches": kernels[dom]["launches"],
+            "avg_ms": kernels[dom]["avg_ms"],
             "bytes_per_launch": sweep_bytes,
         },
+        "kernels": {c: dict(v, traffic=pmc_traffic(c)) for c, v in kernels.items()},
         "cpu_baseline": cpu,
         "stats_last_step": st,
         **extra,

@@ -8,7 +8,9 @@ and writes the per-launch HBM bytes of the chosen kernel as JSON and
 markdown.  The JSON carries the hash of the kernel source it was taken on;
 bench.py reports the figure only while that source is unchanged.
 
-usage: python -m paper_2608_16940_amd.pmc_summary FETCH_CSV WRITE_CSV KERNEL_SUBSTR STATE_BYTES OUT_STEM "COMMAND..."
+usage: python -m paper_2608_16940_amd.pmc_summary FETCH_CSV WRITE_CSV KERNEL_SUBSTR STATE_BYTES OUT_STEM "COMMAND..." [SOURCE]
+
+SOURCE is the kernel's source file under paper_2608_16940_amd/csrc (default sv_tile.hip).
 """
 from __future__ import annotations
 
@@ -20,7 +22,7 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SRC = os.path.join(ROOT, "paper_2608_16940_amd", "csrc", "sv_tile.hip")
+CSRC = os.path.join(ROOT, "paper_2608_16940_amd", "csrc")
 
 
 def _rows(path):
@@ -37,6 +39,7 @@ def per_launch(path, kernel_substr):
 
 def main(argv):
     fetch_csv, write_csv, ksub, state_bytes, stem, cmd = argv[1:7]
+    src = argv[7] if len(argv) > 7 else "sv_tile.hip"
     state_bytes = float(state_bytes)
     fv, fcopy = per_launch(fetch_csv, ksub)
     wv, wcopy = per_launch(write_csv, ksub)
@@ -44,10 +47,10 @@ def main(argv):
     wscale = state_bytes / wcopy
     f = statistics.mean(fv) * fscale
     w = statistics.mean(wv) * wscale
-    with open(KERNEL_SRC, "rb") as fh:
+    with open(os.path.join(CSRC, src), "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()[:16]
     out = {
-        "kernel": ksub, "launches": len(fv), "source_sha": sha,
+        "kernel": ksub, "launches": len(fv), "source": src, "source_sha": sha,
         "fetch_bytes_per_launch": f, "write_bytes_per_launch": w, "bytes_per_launch": f + w,
         "fetch_scale_from_copy": fscale, "write_scale_from_copy": wscale,
         "copy_probe_bytes_each_way": state_bytes, "command": cmd,
@@ -67,7 +70,7 @@ def main(argv):
         fh.write("| HBM read bytes per launch | %.4e |\n" % f)
         fh.write("| HBM write bytes per launch | %.4e |\n" % w)
         fh.write("| total per launch | %.4e (algorithmic %.4e) |\n" % (f + w, 2 * state_bytes))
-        fh.write("| kernel source sha256[:16] | %s |\n" % sha)
+        fh.write("| kernel source %s sha256[:16] | %s |\n" % (src, sha))
     print(json.dumps(out))
 
 
