@@ -525,6 +525,20 @@ def bench_c1(args):
         sv.sample(0x5EED, shots)
     t_sample = (time.perf_counter() - t0) / reps
     st = sv.stats()
+    # the same circuit as a bound plan (operands resident, launches only) and as one HIP graph
+    bound = plan.bind(sv)
+    timings = {}
+    for name, fn in (("bound", bound.run), ("graph", bound.run_graph)):
+        sv.reset()
+        fn()
+        sv.sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sv.reset()
+            fn()
+        sv.sync()
+        timings[name] = (time.perf_counter() - t0) / reps
+    bound.close()
     sv.close()
     out = {
         "metric": "gate-by-gate applies per second, N=%d c64 (cache-resident)" % n,
@@ -533,6 +547,8 @@ def bench_c1(args):
         "config": {"workload": "N=%d brickwork 20 layers (Haar SU(2) + CZ, seed %d), no fusion; %d shots"
                                % (n, args.seed, shots), "gates": len(gates)},
         "us_per_gate": t_gates / len(gates) * 1e6, "ms_per_circuit": t_gates * 1e3,
+        "bound_plan": {"us_per_gate": timings["bound"] / len(gates) * 1e6, "gates_per_s": len(gates) / timings["bound"]},
+        "hip_graph": {"us_per_gate": timings["graph"] / len(gates) * 1e6, "gates_per_s": len(gates) / timings["graph"]},
         "ms_per_10k_samples": t_sample * 1e3, "by_variant_last": st["by_variant"],
     }
     print(json.dumps(out), flush=True)

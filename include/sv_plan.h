@@ -97,6 +97,35 @@ int sv_run_plan(sv_state *s, const sv_plan *p);
 
 int sv_plan_free(sv_plan *p);
 
+/*
+ * Bound plan: every block of a plan lowered once for one state handle (its
+ * current layout, options and precision), with all device operands uploaded
+ * into caller memory.  A run is then a sequence of kernel launches on the
+ * handle's stream with no host work or copy per block, so it can be captured
+ * into a HIP graph and replayed (launch-bound circuits: small states, many
+ * narrow gates).  Lazy relabel must be off; a run requires the layout map to
+ * be the one the plan was bound with.
+ *   sv_bound_bytes      device bytes the operands need (*out; 0 if all by value)
+ *   sv_plan_bind        lower every block, copy the operands into op_dev
+ *                       (caller-owned device memory, >= sv_bound_bytes,
+ *                       256-B aligned; the copy completes before return)
+ *   sv_bound_run        launch every block in order (asynchronous)
+ *   sv_bound_graph_run  first call: capture the launches into a HIP graph on
+ *                       the handle's stream and instantiate it; every call:
+ *                       launch the graph (asynchronous).  The graph holds
+ *                       kernel nodes only.
+ *   sv_bound_free       release the host object (and the graph)
+ * The bound plan keeps pointers to the handle and to op_dev: free it before
+ * either.  Errors: SV_ERR_ARG (relabel on, buffer too small or misaligned,
+ * layout changed since binding), SV_ERR_UNSUPPORTED, SV_ERR_DEVICE.
+ */
+typedef struct sv_bound sv_bound;
+int sv_bound_bytes(sv_state *s, const sv_plan *p, size_t *out);
+int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, sv_bound **out);
+int sv_bound_run(sv_bound *b);
+int sv_bound_graph_run(sv_bound *b);
+int sv_bound_free(sv_bound *b);
+
 #ifdef __cplusplus
 }
 #endif

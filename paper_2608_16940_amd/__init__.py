@@ -259,9 +259,44 @@ class Plan:
     def run(self, sv: "StateVector"):
         check(lib().sv_run_plan(sv._h, self._h))
 
+    def bind(self, sv: "StateVector") -> "BoundPlan":
+        """Lower every block once for ``sv`` (its layout, options, precision) with operands in device memory."""
+        return BoundPlan(self, sv)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().sv_plan_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BoundPlan:
+    """A plan bound to one state: runs are kernel launches only, and can replay as one HIP graph."""
+
+    def __init__(self, plan: Plan, sv: StateVector):
+        import torch
+        need = ctypes.c_size_t()
+        check(lib().sv_bound_bytes(sv._h, plan._h, ctypes.byref(need)))
+        self.sv = sv
+        self.ops = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=sv.amps.device)
+        self._h = ctypes.c_void_p()
+        check(lib().sv_plan_bind(sv._h, plan._h, ctypes.c_void_p(self.ops.data_ptr()), int(self.ops.numel()),
+                                 ctypes.byref(self._h)))
+
+    def run(self):
+        check(lib().sv_bound_run(self._h))
+
+    def run_graph(self):
+        check(lib().sv_bound_graph_run(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sv_bound_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -85,6 +85,11 @@ SIGNATURES = [
     ("sv_plan_block_matrix", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("sv_run_plan", ctypes.c_int, [_vp, _vp]),
     ("sv_plan_free", ctypes.c_int, [_vp]),
+    ("sv_bound_bytes", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
+    ("sv_plan_bind", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    ("sv_bound_run", ctypes.c_int, [_vp]),
+    ("sv_bound_graph_run", ctypes.c_int, [_vp]),
+    ("sv_bound_free", ctypes.c_int, [_vp]),
     ("sv_hint_next_use", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     ("sv_mlp_param_count", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     ("sv_mlp_cache_floats", ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),

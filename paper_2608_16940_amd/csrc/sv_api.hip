@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "sv_internal.h"
+#include "sv_plan.h"
 
 namespace sv {
 
@@ -185,7 +186,24 @@ std::vector<std::pair<int, int>> plan_relabel(const sv_state *s, const int32_t *
   return pairs;
 }
 
-int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
+// A gate resolved to one kernel launch: the chosen lowering, its physical
+// targets, operands passed by value, and the host bytes of an operand that
+// has to sit in device memory (MFMA operand, generic matrix, wide diagonal).
+struct Lowered {
+  int variant = SV_VARIANT_AUTO;
+  int k = 0;
+  int32_t A[8] = {0};
+  float2 m[256];               // by value: VALU matrix, shuffle 2x2, diagonal table with k <= 4
+  bool by_value = false;
+  std::vector<char> op;        // device operand bytes (empty when by value)
+  TilePlan tp;                 // MFMA tile geometry
+  int prec = SV_PREC_FP32, opsrc = SV_MFMA_OPERAND_AUTO;
+  std::vector<std::pair<int, int>> relabel;  // MFMA store-side bit exchanges
+};
+
+// Choose the kernel for a gate on physical targets A and prepare its
+// operands (the selector of the lowering step; Section IV-E).
+int lower(const sv_state *s, const double *matrix, const int32_t *A, int k, bool allow_relabel, Lowered *L) {
   const int n = s->n;
   int v = s->variant;
   const bool shuffle_ok = (k == 1 && A[0] <= 6);
@@ -211,7 +229,11 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
     else
       v = SV_VARIANT_GENERIC;
   }
-  hipError_t e = hipSuccess;
+  L->variant = v;
+  L->k = k;
+  for (int j = 0; j < k; ++j) L->A[j] = A[j];
+  L->prec = s->prec;
+  L->opsrc = s->opsrc;
   switch (v) {
     case SV_VARIANT_DIAG: {
       if (!diag) {
@@ -221,73 +243,51 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
       std::vector<float2> d(static_cast<size_t>(D));
       for (int r = 0; r < D; ++r)
         d[r] = make_float2(float(matrix[2 * (r * D + r)]), float(matrix[2 * (r * D + r) + 1]));
-      if (k <= 4) {  // small tables ride in the kernel arguments: no staging copy
-        e = launch_diag(s->amps, n, k, A, nullptr, d.data(), s->st);
-        break;
+      if (k <= 4) {  // small tables ride in the kernel arguments
+        L->by_value = true;
+        for (int r = 0; r < D; ++r) L->m[r] = d[r];
+      } else {
+        L->op.resize(d.size() * sizeof(float2));
+        std::memcpy(L->op.data(), d.data(), L->op.size());
       }
-      void *dev = nullptr;
-      int slot = 0;
-      int rc = stage(s, d.data(), d.size() * sizeof(float2), &dev, &slot);
-      if (rc) return rc;
-      e = launch_diag(s->amps, n, k, A, static_cast<const float2 *>(dev), nullptr, s->st);
-      if (e == hipSuccess) {
-        rc = release_slot(s, slot);
-        if (rc) return rc;
-      }
-      break;
+      return SV_OK;
     }
     case SV_VARIANT_SHUFFLE:
-    case SV_VARIANT_VALU: {
+    case SV_VARIANT_VALU:
       if ((v == SV_VARIANT_SHUFFLE && !shuffle_ok) || (v == SV_VARIANT_VALU && !valu_ok)) {
         set_error("forced variant does not apply to this gate");
         return SV_ERR_UNSUPPORTED;
       }
-      float2 m[256];
-      for (int i = 0; i < D * D; ++i) m[i] = make_float2(float(matrix[2 * i]), float(matrix[2 * i + 1]));
-      e = (v == SV_VARIANT_SHUFFLE) ? launch_1q_shuffle(s->amps, n, A[0], m, s->st)
-                                    : launch_dense_valu(s->amps, n, k, A, m, s->st);
-      break;
-    }
+      L->by_value = true;
+      for (int i = 0; i < D * D; ++i) L->m[i] = make_float2(float(matrix[2 * i]), float(matrix[2 * i + 1]));
+      return SV_OK;
     case SV_VARIANT_MFMA: {
       if (!mfma_ok) {
         set_error("MFMA lowering needs 4 <= k <= 7 and a state of at least k + tile bits");
         return SV_ERR_UNSUPPORTED;
       }
-      TilePlan tp;
-      std::vector<std::pair<int, int>> pairs;
-      if (s->lazy) pairs = plan_relabel(s, A, k, mfma_tile_M(k));
+      if (s->lazy && allow_relabel) L->relabel = plan_relabel(s, A, k, mfma_tile_M(k));
       uint64_t extra = 0;
-      for (auto &pr : pairs) extra |= uint64_t(1) << pr.second;
-      if (!make_gate_tile(n, k, A, extra, &tp)) {
+      for (auto &pr : L->relabel) extra |= uint64_t(1) << pr.second;
+      if (!make_gate_tile(n, k, A, extra, &L->tp)) {
         set_error("tile geometry failed");
         return SV_ERR_UNSUPPORTED;
       }
       // store side: output tile-order bit of position a reads the local bit that
       // held position v on load, and vice versa (a physical bit exchange)
-      for (auto &pr : pairs) {
+      for (auto &pr : L->relabel) {
         int ba = -1, bv = -1;
-        for (int b = 0; b < tp.s; ++b) {
-          if (tp.sbit[b] == pr.first) ba = b;
-          if (tp.sbit[b] == pr.second) bv = b;
+        for (int b = 0; b < L->tp.s; ++b) {
+          if (L->tp.sbit[b] == pr.first) ba = b;
+          if (L->tp.sbit[b] == pr.second) bv = b;
         }
-        const int t = tp.loc_out[ba];
-        tp.loc_out[ba] = tp.loc_out[bv];
-        tp.loc_out[bv] = t;
+        const int t = L->tp.loc_out[ba];
+        L->tp.loc_out[ba] = L->tp.loc_out[bv];
+        L->tp.loc_out[bv] = t;
       }
-      std::vector<char> buf(mfma_operand_bytes(k, s->prec));
-      pack_mfma_operand(k, s->prec, matrix, buf.data());
-      void *dev = nullptr;
-      int slot = 0;
-      int rc = stage(s, buf.data(), buf.size(), &dev, &slot);
-      if (rc) return rc;
-      e = launch_tile_mfma(tp, s->prec, s->opsrc, s->amps, dev, s->st);
-      if (e == hipSuccess) {
-        rc = release_slot(s, slot);
-        if (rc) return rc;
-        for (auto &pr : pairs) swap_physical(s, pr.first, pr.second);
-        s->stats.relabels += int64_t(pairs.size());
-      }
-      break;
+      L->op.resize(mfma_operand_bytes(k, s->prec));
+      pack_mfma_operand(k, s->prec, matrix, L->op.data());
+      return SV_OK;
     }
     case SV_VARIANT_GENERIC: {
       if (k > 8) {
@@ -296,20 +296,32 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
       }
       std::vector<float2> m(size_t(D) * D);
       for (size_t i = 0; i < m.size(); ++i) m[i] = make_float2(float(matrix[2 * i]), float(matrix[2 * i + 1]));
-      void *dev = nullptr;
-      int slot = 0;
-      int rc = stage(s, m.data(), m.size() * sizeof(float2), &dev, &slot);
-      if (rc) return rc;
-      e = launch_dense_generic(s->amps, n, k, A, static_cast<const float2 *>(dev), s->st);
-      if (e == hipSuccess) {
-        rc = release_slot(s, slot);
-        if (rc) return rc;
-      }
-      break;
+      L->op.resize(m.size() * sizeof(float2));
+      std::memcpy(L->op.data(), m.data(), L->op.size());
+      return SV_OK;
     }
     default:
       set_error("unknown variant");
       return SV_ERR_ARG;
+  }
+}
+
+// Launch a lowered gate; op_dev holds L.op in device memory when it is not by value.
+int launch_lowered(sv_state *s, const Lowered &L, const void *op_dev) {
+  const int n = s->n;
+  hipError_t e = hipSuccess;
+  switch (L.variant) {
+    case SV_VARIANT_DIAG:
+      e = L.by_value ? launch_diag(s->amps, n, L.k, L.A, nullptr, L.m, s->st)
+                     : launch_diag(s->amps, n, L.k, L.A, static_cast<const float2 *>(op_dev), nullptr, s->st);
+      break;
+    case SV_VARIANT_SHUFFLE: e = launch_1q_shuffle(s->amps, n, L.A[0], L.m, s->st); break;
+    case SV_VARIANT_VALU: e = launch_dense_valu(s->amps, n, L.k, L.A, L.m, s->st); break;
+    case SV_VARIANT_MFMA: e = launch_tile_mfma(L.tp, L.prec, L.opsrc, s->amps, op_dev, s->st); break;
+    case SV_VARIANT_GENERIC:
+      e = launch_dense_generic(s->amps, n, L.k, L.A, static_cast<const float2 *>(op_dev), s->st);
+      break;
+    default: e = hipErrorInvalidValue;
   }
   if (e != hipSuccess) {
     set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -317,7 +329,25 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
   }
   s->stats.gate_sweeps += 1;
   s->stats.launches += 1;
-  if (v >= 0 && v < 6) s->stats.by_variant[v] += 1;
+  if (L.variant >= 0 && L.variant < 6) s->stats.by_variant[L.variant] += 1;
+  return SV_OK;
+}
+
+int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
+  Lowered L;
+  int rc = lower(s, matrix, A, k, true, &L);
+  if (rc) return rc;
+  if (L.op.empty()) return launch_lowered(s, L, nullptr);
+  void *dev = nullptr;
+  int slot = 0;
+  rc = stage(s, L.op.data(), L.op.size(), &dev, &slot);
+  if (rc) return rc;
+  rc = launch_lowered(s, L, dev);
+  if (rc) return rc;
+  rc = release_slot(s, slot);
+  if (rc) return rc;
+  for (auto &pr : L.relabel) swap_physical(s, pr.first, pr.second);
+  s->stats.relabels += int64_t(L.relabel.size());
   return SV_OK;
 }
 
@@ -756,6 +786,212 @@ int sv_get_stats(const sv_state *s, sv_stats *out) {
     return SV_ERR_ARG;
   }
   *out = s->stats;
+  return SV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ bound plans
+struct sv_bound {
+  sv_state *s = nullptr;
+  std::vector<Lowered> ops;
+  std::vector<size_t> off;  // operand offset in op_dev (SIZE_MAX: by value)
+  char *op_dev = nullptr;
+  int32_t L[64];
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;  // private stream the graph is captured on
+  sv_stats per_run;               // statistics one run adds
+};
+
+namespace {
+
+int lower_plan(sv_state *s, const sv_plan *p, std::vector<Lowered> *ops, std::vector<size_t> *off, size_t *bytes) {
+  if (s->lazy) {
+    set_error("bound plans need lazy relabel off");
+    return SV_ERR_ARG;
+  }
+  int nb = 0;
+  int rc = sv_plan_num_blocks(p, &nb);
+  if (rc) return rc;
+  ops->assign(static_cast<size_t>(nb), Lowered());
+  off->assign(static_cast<size_t>(nb), SIZE_MAX);
+  size_t total = 0;
+  for (int i = 0; i < nb; ++i) {
+    int k = 0, ng = 0, dg = 0;
+    int32_t t[8];
+    rc = sv_plan_block_info(p, i, &k, t, &ng, &dg);
+    if (rc) return rc;
+    std::vector<double> m(size_t(2) << (2 * k));
+    rc = sv_plan_block_matrix(p, i, m.data());
+    if (rc) return rc;
+    int32_t A[8];
+    for (int j = 0; j < k; ++j) {
+      if (t[j] < 0 || t[j] >= s->n) {
+        set_error("plan target outside the state");
+        return SV_ERR_ARG;
+      }
+      A[j] = s->L[t[j]];
+    }
+    rc = lower(s, m.data(), A, k, false, &(*ops)[size_t(i)]);
+    if (rc) return rc;
+    if (!(*ops)[size_t(i)].op.empty()) {
+      (*off)[size_t(i)] = total;
+      total += align256((*ops)[size_t(i)].op.size());
+    }
+  }
+  *bytes = total;
+  return SV_OK;
+}
+
+int bound_check(const sv_bound *b) {
+  if (!b || !b->s) {
+    set_error("null bound plan");
+    return SV_ERR_ARG;
+  }
+  if (std::memcmp(b->L, b->s->L, sizeof(int32_t) * size_t(b->s->n)) != 0) {
+    set_error("layout changed since the plan was bound");
+    return SV_ERR_ARG;
+  }
+  return SV_OK;
+}
+
+int bound_launch_all(sv_bound *b) {
+  for (size_t i = 0; i < b->ops.size(); ++i) {
+    const void *dev = b->off[i] == SIZE_MAX ? nullptr : b->op_dev + b->off[i];
+    const int rc = launch_lowered(b->s, b->ops[i], dev);
+    if (rc) return rc;
+  }
+  return SV_OK;
+}
+
+void add_stats(sv_stats *a, const sv_stats &d) {
+  a->gate_sweeps += d.gate_sweeps;
+  a->launches += d.launches;
+  for (int v = 0; v < 6; ++v) a->by_variant[v] += d.by_variant[v];
+}
+
+}  // namespace
+
+extern "C" {
+
+int sv_bound_bytes(sv_state *s, const sv_plan *p, size_t *out) {
+  if (!s || !p || !out) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  std::vector<Lowered> ops;
+  std::vector<size_t> off;
+  return lower_plan(s, p, &ops, &off, out);
+}
+
+int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, sv_bound **out) {
+  if (!s || !p || !out) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  sv_bound *b = new sv_bound();
+  b->s = s;
+  size_t need = 0;
+  int rc = lower_plan(s, p, &b->ops, &b->off, &need);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  if (need > 0 && (!op_dev || op_bytes < need || (reinterpret_cast<uintptr_t>(op_dev) & 255))) {
+    delete b;
+    set_error("operand buffer missing, too small or not 256-byte aligned");
+    return SV_ERR_ARG;
+  }
+  b->op_dev = static_cast<char *>(op_dev);
+  std::vector<char> host(need);
+  for (size_t i = 0; i < b->ops.size(); ++i) {
+    if (b->off[i] == SIZE_MAX) continue;
+    std::memcpy(host.data() + b->off[i], b->ops[i].op.data(), b->ops[i].op.size());
+    b->ops[i].op.clear();
+    b->ops[i].op.shrink_to_fit();
+  }
+  if (need > 0) {
+    hipError_t e = hipMemcpyAsync(op_dev, host.data(), need, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) {
+      delete b;
+      set_error(std::string("operand upload failed: ") + hipGetErrorString(e));
+      return SV_ERR_DEVICE;
+    }
+  }
+  std::memcpy(b->L, s->L, sizeof(b->L));
+  std::memset(&b->per_run, 0, sizeof(b->per_run));
+  for (const Lowered &L : b->ops) {
+    b->per_run.gate_sweeps += 1;
+    b->per_run.launches += 1;
+    if (L.variant >= 0 && L.variant < 6) b->per_run.by_variant[L.variant] += 1;
+  }
+  *out = b;
+  return SV_OK;
+}
+
+int sv_bound_run(sv_bound *b) {
+  const int rc = bound_check(b);
+  if (rc) return rc;
+  return bound_launch_all(b);
+}
+
+int sv_bound_graph_run(sv_bound *b) {
+  int rc = bound_check(b);
+  if (rc) return rc;
+  sv_state *s = b->s;
+  if (!b->exec) {
+    // The handle's stream may be the legacy default stream, which cannot be
+    // captured: capture on a private stream (default priority), launch the
+    // graph on the handle's stream.
+    hipError_t e = hipSuccess;
+    if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      set_error(std::string("graph capture failed to start: ") + hipGetErrorString(e));
+      return SV_ERR_DEVICE;
+    }
+    const sv_stats saved = s->stats;
+    hipStream_t user = s->st;
+    s->st = b->capture;
+    rc = bound_launch_all(b);
+    s->st = user;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->capture, &g);
+    s->stats = saved;  // nothing ran while capturing
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess || !g) {
+      set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+      return SV_ERR_DEVICE;
+    }
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      b->exec = nullptr;
+      set_error(std::string("graph instantiation failed: ") + hipGetErrorString(e));
+      return SV_ERR_DEVICE;
+    }
+    b->graph = g;
+  }
+  const hipError_t e = hipGraphLaunch(b->exec, s->st);
+  if (e != hipSuccess) {
+    set_error(std::string("graph launch failed: ") + hipGetErrorString(e));
+    return SV_ERR_DEVICE;
+  }
+  add_stats(&s->stats, b->per_run);
+  return SV_OK;
+}
+
+int sv_bound_free(sv_bound *b) {
+  if (!b) return SV_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
   return SV_OK;
 }
 

@@ -364,3 +364,63 @@ def test_permute_layout_small_and_tile_paths(P, n):
         assert st["permute_sweeps"] > 0 and st["swap_half_sweeps"] == 0
     else:
         assert st["permute_sweeps"] == 0
+
+
+# ---------------------------------------------------------------- bound plans and HIP graphs
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_bound_plan_and_graph_replays(P, prec):
+    """A bound plan launches the same kernels with the same operands as plan.run (bit-identical);
+    its HIP-graph replays, with eager work between them, reproduce it bit for bit."""
+    n = 16
+    rng = np.random.default_rng(21)
+    gates = rand_state_gates(n, rng, 2) + W.brickwork(n, 4, 3) + W.qft(n)
+    gates += [W.random_dense(n, 7, rng), W.random_dense(n, 8, rng), W.random_dense(n, 1, rng, (12,)),
+              W.random_dense(n, 1, rng, (3,))]
+    plan = P.Plan.greedy(n, gates, 6)
+    ref_sv = P.StateVector(n)
+    ref_sv.set_precision(prec)
+    plan.run(ref_sv)
+    ref = ref_sv.physical_state()
+    variants = ref_sv.stats()["by_variant"]
+    assert variants[P._native.VARIANT["diag"]] > 0 and variants[P._native.VARIANT["mfma"]] > 0
+    assert variants[P._native.VARIANT["generic"]] > 0
+    sv = P.StateVector(n)
+    sv.set_precision(prec)
+    bound = plan.bind(sv)
+    bound.run()
+    np.testing.assert_array_equal(sv.physical_state(), ref)
+    for rep in range(3):
+        sv.reset()
+        bound.run_graph()
+        got = sv.physical_state()
+        np.testing.assert_array_equal(got, ref)
+        assert abs(sv.norm() - 1) < 2e-4  # eager work between replays
+        sv.sample(rep, 100)
+    assert sv.stats()["gate_sweeps"] == len(plan)  # counters restart at each reset; a replay adds one run
+    if prec == "fp32":
+        check_close(oracle.run(n, gates), oracle.decode(ref, sv.layout()), what="bound plan")
+    bound.close()
+    sv.close()
+    ref_sv.close()
+
+
+def test_bound_plan_guards(P):
+    n = 12
+    rng = np.random.default_rng(5)
+    plan = P.Plan.greedy(n, [W.random_dense(n, 5, rng), W.random_dense(n, 2, rng)], 5)
+    sv = P.StateVector(n)
+    sv.set_relabel(True)
+    with pytest.raises(RuntimeError):
+        plan.bind(sv)
+    sv.set_relabel(False)
+    bound = plan.bind(sv)
+    bound.run()
+    layout = list(range(n))
+    layout[0], layout[n - 1] = layout[n - 1], layout[0]
+    sv.permute_layout(layout)
+    with pytest.raises(RuntimeError):
+        bound.run()
+    with pytest.raises(RuntimeError):
+        bound.run_graph()
+    bound.close()
+    sv.close()
