@@ -1,10 +1,10 @@
 /*
  * libsv fusion planning: turn an ordered gate list into fused blocks.
  *
- * Fusion replaces consecutive gates by their matrix product (Section IV-C):
- * within a block matrices stay in circuit order with later gates multiplied
- * on the left; a block is diagonal when every constituent gate is.  Products
- * are formed on the host in FP64.
+ * A fused block is the matrix product of a run of consecutive gates (Section IV-C),
+ * taken in circuit order with each later gate's matrix multiplying from the
+ * left; a block counts as diagonal when all of its gates do.  The products
+ * are computed on the host in FP64.
  *
  * Gate lists are passed flat:
  *   ks[i]        width of gate i (1..8)
