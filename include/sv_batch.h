@@ -70,6 +70,24 @@ int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, siz
  * and, if times_out is not NULL, the subset's launch time in seconds after
  * each size was tuned.  Uses states_dev / ws_dev like sv_batch_run.
  */
+/*
+ * Host only (no GPU): the gate records the batched kernel runs for one
+ * circuit, after the host fuses adjacent single-qubit gates and, for more
+ * than 2^14 amplitudes, cuts the circuit into LDS slice passes.  Each record
+ * is 4 int32 (kind, q0, q1, unused) plus 8 floats:
+ *   kind SV_BATCH_GATE_1Q   q0 = qubit, floats = 2x2 complex64 row-major
+ *   kind SV_BATCH_GATE_CNOT q0 = control, q1 = target
+ *   kind SV_BATCH_PASS      q0 = bit mask of the 14 slice qubits, q1 = number
+ *                           of following records in the pass; their qubit
+ *                           numbers are slice bit positions (rank of the qubit
+ *                           in the mask)
+ * records: int32[4 * cap], mats: float[8 * cap]; *n_out = records written.
+ * cap >= 2 * c->n_gates always suffices.  Errors: SV_ERR_ARG (bad circuit,
+ * cap too small).
+ */
+#define SV_BATCH_PASS 2
+int sv_batch_records(const sv_batch_circuit *c, int cap, int32_t *records, float *mats, int *n_out);
+
 int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
                       const int64_t *state_offsets, int sample_per_size, int32_t *config_out, double *times_out,
                       void *ws_dev, size_t ws_bytes, void *stream);

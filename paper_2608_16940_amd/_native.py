@@ -85,6 +85,8 @@ SIGNATURES = [
     ("sv_plan_block_matrix", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("sv_run_plan", ctypes.c_int, [_vp, _vp]),
     ("sv_plan_free", ctypes.c_int, [_vp]),
+    ("sv_batch_records", ctypes.c_int, [_vp, ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_int)]),
     ("sv_bound_bytes", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("sv_plan_bind", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     ("sv_bound_run", ctypes.c_int, [_vp]),

@@ -59,6 +59,17 @@ class Batch:
         self.offsets = offsets
         self.state_bytes = max(off, 8)
 
+    def records(self, i: int):
+        """Host only: the gate records the kernel runs for circuit i (after 1q fusion and slice passes)
+        as (int32[m, 4] kind/q0/q1/0, float32[m, 8] 2x2 complex64 matrices)."""
+        cap = 2 * max(1, int(self.arr[i].n_gates)) + 2
+        rec = np.zeros((cap, 4), dtype=np.int32)
+        mats = np.zeros((cap, 8), dtype=np.float32)
+        m = ctypes.c_int()
+        check(lib().sv_batch_records(ctypes.byref(self.arr[i]), cap, rec.ctypes.data_as(_native._i32p),
+                                     mats.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(m)))
+        return rec[:m.value], mats[:m.value]
+
     def allocate(self, device="cuda:0"):
         torch = _torch()
         self.states = torch.empty(self.state_bytes // 8, dtype=torch.complex64, device=device)

@@ -51,7 +51,7 @@ __device__ __forceinline__ float2 cmad(float ar, float ai, float2 x, float2 acc)
 }
 
 constexpr int kSliceBits = 14;
-constexpr int kGatePass = 2;  // internal record: q0 = slice qubit mask, q1 = gates in the pass
+constexpr int kGatePass = SV_BATCH_PASS;  // record: q0 = slice qubit mask, q1 = gates in the pass
 
 // One gate on a state of `dim` amplitudes at st (LDS or global), threads lt of Tc.
 __device__ __forceinline__ void apply_gate(const BGate &G, float2 *st, int64_t dim, int lt, int Tc) {
@@ -558,3 +558,34 @@ int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev
 }
 
 }  // extern "C"
+
+extern "C" int sv_batch_records(const sv_batch_circuit *c, int cap, int32_t *records, float *mats, int *n_out) {
+  if (!c || !records || !mats || !n_out || cap < 0) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  if (c->n_qubits < 1 || c->n_qubits > SV_BATCH_MAX_QUBITS) {
+    set_error("bad batch circuit");
+    return SV_ERR_ARG;
+  }
+  int32_t cfg[SV_BATCH_CONFIG_LEN];
+  default_config(cfg);
+  const int64_t off = 0;
+  Packed pk;
+  const int rc = pack_batch(1, c, size_t(8) << c->n_qubits, &off, cfg, &pk);
+  if (rc) return rc;
+  if (pk.gates.size() > size_t(cap)) {
+    set_error("record capacity too small");
+    return SV_ERR_ARG;
+  }
+  for (size_t i = 0; i < pk.gates.size(); ++i) {
+    const BGate &g = pk.gates[i];
+    records[4 * i + 0] = g.kind;
+    records[4 * i + 1] = g.q0;
+    records[4 * i + 2] = g.q1;
+    records[4 * i + 3] = 0;
+    for (int e = 0; e < 8; ++e) mats[8 * i + size_t(e)] = g.m[e];
+  }
+  *n_out = int(pk.gates.size());
+  return SV_OK;
+}

@@ -1,0 +1,113 @@
+"""Batched path, host side (no GPU): the records the kernel runs.
+
+Circuits with more than 2^14 amplitudes are cut into LDS slice passes.  This
+test replays the records exactly as the kernel does — gather each slice of
+14 qubits, apply the pass's gates in slice coordinates, scatter back — in
+complex128 numpy, and compares with the oracle applying the original gates.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+SLICE = 14
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_2608_16940_amd as P
+    P.lib()
+    from paper_2608_16940_amd import batch as B
+    return B
+
+
+def apply_1q(v, q, m, nb):
+    t = v.reshape(-1, 2, 1 << q)
+    a, b = t[:, 0, :].copy(), t[:, 1, :].copy()
+    t[:, 0, :] = m[0, 0] * a + m[0, 1] * b
+    t[:, 1, :] = m[1, 0] * a + m[1, 1] * b
+
+
+def apply_cnot(v, c, t_, nb):
+    idx = np.arange(1 << nb)
+    sel = ((idx >> c) & 1 == 1) & ((idx >> t_) & 1 == 0)
+    x = idx[sel]
+    y = x | (1 << t_)
+    v[x], v[y] = v[y].copy(), v[x].copy()
+
+
+def apply_record(v, rec, mat, nb):
+    if rec[0] == 0:
+        m = mat.astype(np.float64).view(np.complex128).reshape(2, 2)
+        apply_1q(v, int(rec[1]), m, nb)
+    elif rec[0] == 1:
+        apply_cnot(v, int(rec[1]), int(rec[2]), nb)
+    else:
+        raise AssertionError("unexpected record kind %d" % rec[0])
+
+
+def replay(n, recs, mats):
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1
+    if n <= SLICE:
+        for r, m in zip(recs, mats):
+            apply_record(psi, r, m, n)
+        return psi, 0
+    i, passes = 0, 0
+    while i < len(recs):
+        assert recs[i][0] == 2, "pass record expected"
+        mask, cnt = int(recs[i][1]), int(recs[i][2])
+        pos = [q for q in range(n) if (mask >> q) & 1]
+        rest = [q for q in range(n) if not (mask >> q) & 1]
+        assert len(pos) == SLICE and pos[:3] == [0, 1, 2]
+        x = np.arange(1 << SLICE)
+        local = np.zeros_like(x)
+        for j, q in enumerate(pos):
+            local |= ((x >> j) & 1) << q
+        for sl in range(1 << len(rest)):
+            base = 0
+            for r, q in enumerate(rest):
+                base |= ((sl >> r) & 1) << q
+            v = psi[base + local].copy()
+            for r, m in zip(recs[i + 1:i + 1 + cnt], mats[i + 1:i + 1 + cnt]):
+                assert 0 <= r[1] < SLICE and (r[0] != 1 or 0 <= r[2] < SLICE)
+                apply_record(v, r, m, SLICE)
+            psi[base + local] = v
+        i += 1 + cnt
+        passes += 1
+    return psi, passes
+
+
+def ladder(n, depth, rng, reverse=False):
+    gates = []
+    for layer in range(depth):
+        for q in range(n):
+            gates.append(W.Gate("ry", (q,), W.ry(float(rng.uniform(0, 2 * np.pi)))))
+            gates.append(W.Gate("rz", (q,), W.rz(float(rng.uniform(0, 2 * np.pi)))))
+        order = range(n - 2, -1, -1) if (reverse and layer % 2) else range(n - 1)
+        for q in order:
+            gates.append(W.Gate("cnot", (q + 1, q) if (reverse and layer % 2) else (q, q + 1), W.cnot()))
+        if reverse:
+            gates.append(W.Gate("cnot", (n - 1, 0), W.cnot()))
+    return gates
+
+
+@pytest.mark.parametrize("n,depth,reverse", [(6, 4, False), (14, 3, True), (15, 5, False), (16, 4, True),
+                                             (17, 3, True)])
+def test_records_replay_equals_oracle(B, n, depth, reverse):
+    rng = np.random.default_rng(100 + n)
+    gates = ladder(n, depth, rng, reverse)
+    b = B.Batch([(n, gates)])
+    recs, mats = b.records(0)
+    got, passes = replay(n, recs, mats)
+    ref = oracle.run(n, gates)
+    m = oracle.metrics(ref, got)
+    assert m["infidelity"] <= 1e-10 and m["max_abs"] <= 1e-6, m
+    ops = [r for r in recs if r[0] != 2]
+    # RY and RZ on the same qubit fuse into one single-qubit record
+    assert len(ops) == depth * n + sum(1 for g in gates if g.kind == "cnot")
+    if n > SLICE:
+        assert 1 <= passes <= len(ops)
+    else:
+        assert passes == 0
