@@ -71,6 +71,21 @@ int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, siz
  * each size was tuned.  Uses states_dev / ws_dev like sv_batch_run.
  */
 /*
+ * The same launch split in two, so that repeated runs of one batch (new
+ * states each time, same circuits) do no host work: sv_batch_prepare packs
+ * the circuits on the host and copies the records into ws_dev (complete
+ * before return); sv_batch_launch resets the queue, runs the persistent
+ * kernel on `stream` and, if z0_host is not NULL, copies <Z_0> per circuit
+ * there and synchronises.  The prepared object refers to ws_dev and the
+ * state offsets given at preparation: keep ws_dev alive and unchanged.
+ */
+typedef struct sv_batch_prepared sv_batch_prepared;
+int sv_batch_prepare(int count, const sv_batch_circuit *circs, size_t states_bytes, const int64_t *state_offsets,
+                     const int32_t *config, void *ws_dev, size_t ws_bytes, void *stream, sv_batch_prepared **out);
+int sv_batch_launch(sv_batch_prepared *p, void *states_dev, double *z0_host, void *stream);
+int sv_batch_prepared_free(sv_batch_prepared *p);
+
+/*
  * Host only (no GPU): the gate records the batched kernel runs for one
  * circuit, after the host fuses adjacent single-qubit gates and, for more
  * than 2^14 amplitudes, cuts the circuit into LDS slice passes.  Each record

@@ -85,6 +85,10 @@ SIGNATURES = [
     ("sv_plan_block_matrix", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("sv_run_plan", ctypes.c_int, [_vp, _vp]),
     ("sv_plan_free", ctypes.c_int, [_vp]),
+    ("sv_batch_prepare", ctypes.c_int, [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64), _i32p,
+                                        _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    ("sv_batch_launch", ctypes.c_int, [_vp, _vp, _dp, _vp]),
+    ("sv_batch_prepared_free", ctypes.c_int, [_vp]),
     ("sv_batch_records", ctypes.c_int, [_vp, ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_int)]),
     ("sv_bound_bytes", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),

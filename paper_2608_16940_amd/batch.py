@@ -95,6 +95,38 @@ class Batch:
                                  ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), sp))
         return z0
 
+    def prepare(self, config=None):
+        """Pack and upload once; then launch() runs the kernel only."""
+        sd, sb, so, sp = self._common()
+        self.close_prepared()
+        cfg = None
+        if config is not None:
+            cfg = np.ascontiguousarray(np.asarray(config, dtype=np.int32))
+            assert cfg.size == _native.BATCH_CONFIG_LEN
+        self._prep = ctypes.c_void_p()
+        check(lib().sv_batch_prepare(self.count, self.arr, sb, so,
+                                     cfg.ctypes.data_as(_native._i32p) if cfg is not None else None,
+                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), sp,
+                                     ctypes.byref(self._prep)))
+        return self
+
+    def launch(self, want_z0: bool = True):
+        sd, sb, so, sp = self._common()
+        z0 = np.zeros(self.count, dtype=np.float64) if want_z0 else None
+        check(lib().sv_batch_launch(self._prep, sd, z0.ctypes.data_as(_native._dp) if want_z0 else None, sp))
+        return z0
+
+    def close_prepared(self):
+        if getattr(self, "_prep", None) is not None and self._prep.value:
+            lib().sv_batch_prepared_free(self._prep)
+        self._prep = None
+
+    def __del__(self):
+        try:
+            self.close_prepared()
+        except Exception:
+            pass
+
     def autotune(self, sample_per_size: int = 32):
         sd, sb, so, sp = self._common()
         cfg = np.zeros(_native.BATCH_CONFIG_LEN, dtype=np.int32)

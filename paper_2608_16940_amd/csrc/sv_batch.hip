@@ -409,26 +409,43 @@ int pack_batch(int count, const sv_batch_circuit *circs, size_t states_bytes, co
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int run_packed(const Packed &pk, void *states_dev, double *z0_dev_or_null, double *z0_host, void *ws_dev,
-               size_t ws_bytes, hipStream_t st, float *ms_out) {
+// Device side of a packed batch: where its records sit in the workspace.
+struct DevBatch {
+  unsigned *counter = nullptr;
+  double *z0 = nullptr;
+  BItem *items = nullptr;
+  BGate *gates = nullptr;
+  int nitems = 0, ncirc = 0;
+};
+
+// Copy a packed batch's records into the workspace (asynchronous on st).
+int upload_packed(const Packed &pk, void *ws_dev, size_t ws_bytes, hipStream_t st, DevBatch *d) {
   const size_t o_cnt = 0;
   const size_t o_z0 = 256;
   const size_t o_items = o_z0 + align256(sizeof(double) * size_t(std::max(1, pk.ncirc)));
   const size_t o_gates = o_items + align256(sizeof(BItem) * std::max<size_t>(1, pk.items.size()));
   const size_t need = o_gates + align256(sizeof(BGate) * std::max<size_t>(1, pk.gates.size()));
-  if (ws_bytes < need) {
+  if (!ws_dev || ws_bytes < need) {
     set_error("batch workspace too small");
     return SV_ERR_ARG;
   }
   char *ws = static_cast<char *>(ws_dev);
-  unsigned *counter = reinterpret_cast<unsigned *>(ws + o_cnt);
-  double *z0 = z0_dev_or_null ? z0_dev_or_null : reinterpret_cast<double *>(ws + o_z0);
-  BItem *items = reinterpret_cast<BItem *>(ws + o_items);
-  BGate *gates = reinterpret_cast<BGate *>(ws + o_gates);
+  d->counter = reinterpret_cast<unsigned *>(ws + o_cnt);
+  d->z0 = reinterpret_cast<double *>(ws + o_z0);
+  d->items = reinterpret_cast<BItem *>(ws + o_items);
+  d->gates = reinterpret_cast<BGate *>(ws + o_gates);
+  d->nitems = int(pk.items.size());
+  d->ncirc = pk.ncirc;
   if (!pk.items.empty())
-    SV_HIP_CHECK(hipMemcpyAsync(items, pk.items.data(), sizeof(BItem) * pk.items.size(), hipMemcpyHostToDevice, st));
+    SV_HIP_CHECK(hipMemcpyAsync(d->items, pk.items.data(), sizeof(BItem) * pk.items.size(), hipMemcpyHostToDevice, st));
   if (!pk.gates.empty())
-    SV_HIP_CHECK(hipMemcpyAsync(gates, pk.gates.data(), sizeof(BGate) * pk.gates.size(), hipMemcpyHostToDevice, st));
+    SV_HIP_CHECK(hipMemcpyAsync(d->gates, pk.gates.data(), sizeof(BGate) * pk.gates.size(), hipMemcpyHostToDevice, st));
+  return SV_OK;
+}
+
+// One persistent launch over an uploaded batch; z0_host (optional) receives
+// <Z_0> per circuit and makes the call synchronous; ms_out (optional) times the kernel.
+int launch_packed(const DevBatch &d, void *states_dev, double *z0_host, hipStream_t st, float *ms_out) {
   int dev = 0, cus = 256;
   SV_HIP_CHECK(hipGetDevice(&dev));
   SV_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -437,23 +454,31 @@ int run_packed(const Packed &pk, void *states_dev, double *z0_dev_or_null, doubl
     SV_HIP_CHECK(hipEventCreate(&e0));
     SV_HIP_CHECK(hipEventCreate(&e1));
   }
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, d.counter);
   SV_HIP_CHECK(hipGetLastError());
   if (ms_out) SV_HIP_CHECK(hipEventRecord(e0, st));
-  const int grid = std::max(1, std::min<int>(cus, int(pk.items.size())));
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), 0, st, items, int(pk.items.size()), gates,
-                     static_cast<float2 *>(states_dev), z0, counter);
+  const int grid = std::max(1, std::min<int>(cus, d.nitems));
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), 0, st, d.items, d.nitems, d.gates,
+                     static_cast<float2 *>(states_dev), d.z0, d.counter);
   SV_HIP_CHECK(hipGetLastError());
   if (ms_out) SV_HIP_CHECK(hipEventRecord(e1, st));
-  if (z0_host && pk.ncirc > 0)
-    SV_HIP_CHECK(hipMemcpyAsync(z0_host, z0, sizeof(double) * size_t(pk.ncirc), hipMemcpyDeviceToHost, st));
-  SV_HIP_CHECK(hipStreamSynchronize(st));
+  if (z0_host && d.ncirc > 0)
+    SV_HIP_CHECK(hipMemcpyAsync(z0_host, d.z0, sizeof(double) * size_t(d.ncirc), hipMemcpyDeviceToHost, st));
+  if (z0_host || ms_out) SV_HIP_CHECK(hipStreamSynchronize(st));
   if (ms_out) {
     SV_HIP_CHECK(hipEventElapsedTime(ms_out, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
   return SV_OK;
+}
+
+int run_packed(const Packed &pk, void *states_dev, double *z0_host, void *ws_dev, size_t ws_bytes, hipStream_t st,
+               float *ms_out) {
+  DevBatch d;
+  const int rc = upload_packed(pk, ws_dev, ws_bytes, st, &d);
+  if (rc) return rc;
+  return launch_packed(d, states_dev, z0_host, st, ms_out);
 }
 
 }  // namespace
@@ -491,7 +516,7 @@ int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, siz
   Packed pk;
   int rc = pack_batch(count, circs, states_bytes, state_offsets, cfg, &pk);
   if (rc) return rc;
-  return run_packed(pk, states_dev, nullptr, z0_host, ws_dev, ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+  return run_packed(pk, states_dev, z0_host, ws_dev, ws_bytes, static_cast<hipStream_t>(stream), nullptr);
 }
 
 int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
@@ -523,9 +548,9 @@ int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev
     int rc = pack_batch(int(sample.size()), sample.data(), states_bytes, offs.data(), c, &pk);
     if (rc) return rc;
     float ms = 0.f;
-    rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);  // warm-up
+    rc = run_packed(pk, states_dev, z.data(), ws_dev, ws_bytes, st, &ms);  // warm-up
     if (rc) return rc;
-    rc = run_packed(pk, states_dev, nullptr, z.data(), ws_dev, ws_bytes, st, &ms);
+    rc = run_packed(pk, states_dev, z.data(), ws_dev, ws_bytes, st, &ms);
     if (rc) return rc;
     *t_out = double(ms) * 1e-3;
     return SV_OK;
@@ -558,6 +583,58 @@ int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev
 }
 
 }  // extern "C"
+
+struct sv_batch_prepared {
+  DevBatch d;
+};
+
+extern "C" int sv_batch_prepare(int count, const sv_batch_circuit *circs, size_t states_bytes,
+                                const int64_t *state_offsets, const int32_t *config, void *ws_dev, size_t ws_bytes,
+                                void *stream, sv_batch_prepared **out) {
+  if (!out || count < 0 || (count > 0 && (!circs || !state_offsets)) || !ws_dev) {
+    set_error("bad batch argument");
+    return SV_ERR_ARG;
+  }
+  int32_t cfg[SV_BATCH_CONFIG_LEN];
+  if (config) {
+    std::memcpy(cfg, config, sizeof(cfg));
+    if (!valid_config(cfg)) {
+      set_error("bad batch config");
+      return SV_ERR_ARG;
+    }
+  } else {
+    default_config(cfg);
+  }
+  Packed pk;
+  int rc = pack_batch(count, circs, states_bytes, state_offsets, cfg, &pk);
+  if (rc) return rc;
+  sv_batch_prepared *p = new sv_batch_prepared();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = upload_packed(pk, ws_dev, ws_bytes, st, &p->d);
+  if (rc == SV_OK && hipStreamSynchronize(st) != hipSuccess) {
+    set_error("batch upload failed");
+    rc = SV_ERR_DEVICE;
+  }
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return SV_OK;
+}
+
+extern "C" int sv_batch_launch(sv_batch_prepared *p, void *states_dev, double *z0_host, void *stream) {
+  if (!p || !states_dev) {
+    set_error("bad batch argument");
+    return SV_ERR_ARG;
+  }
+  return launch_packed(p->d, states_dev, z0_host, static_cast<hipStream_t>(stream), nullptr);
+}
+
+extern "C" int sv_batch_prepared_free(sv_batch_prepared *p) {
+  delete p;
+  return SV_OK;
+}
 
 extern "C" int sv_batch_records(const sv_batch_circuit *c, int cap, int32_t *records, float *mats, int *n_out) {
   if (!c || !records || !mats || !n_out || cap < 0) {

@@ -16,6 +16,7 @@ namespace sv {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int64_t kFullGrid = int64_t(1) << 23;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int64_t insert_zero_bit(int64_t x, int p) {
@@ -35,9 +36,10 @@ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
 }
 
 // Workgroups for `items` per-thread work units; streaming kernels here run
-// fastest with one unit per thread over a full grid (2^22 workgroups of 256
-// stay inside the 2^32 - 1 work-item dispatch limit; the kernels grid-stride
-// past it).
+// fastest with one unit per thread over a full grid.  kFullGrid = 2^23
+// workgroups of 256 (2^31 work-items) stays inside the 2^32 - 1 dispatch
+// limit and covers every chunk of a 2^32-amplitude state once; larger states
+// grid-stride.
 inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 20) {
   int64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -466,7 +468,7 @@ hipError_t launch_init_zero(float2 *psi, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_init_small, dim3(1), dim3(64), 0, st, psi, dim);
   } else {
     const int64_t n4 = dim / 2;
-    hipLaunchKernelGGL(k_init_zero, dim3(grid_for(n4, kThreads, 1 << 22)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(k_init_zero, dim3(grid_for(n4, kThreads, kFullGrid)), dim3(kThreads), 0, st,
                        reinterpret_cast<float4 *>(psi), n4, psi);
   }
   return hipGetLastError();
@@ -492,7 +494,7 @@ static hipError_t dense_valu_k(float2 *psi, int n, const int32_t *A, const float
     }
   for (int j = 0; j < K; ++j) a.sorted[j] = s[j];
   const int64_t ngroups = int64_t(1) << (n - K);
-  hipLaunchKernelGGL(k_dense_valu<K>, dim3(grid_for(ngroups, kThreads, 1 << 22)), dim3(kThreads), 0, st, psi,
+  hipLaunchKernelGGL(k_dense_valu<K>, dim3(grid_for(ngroups, kThreads, kFullGrid)), dim3(kThreads), 0, st, psi,
                      ngroups, a);
   return hipGetLastError();
 }
@@ -511,7 +513,7 @@ hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStre
   if (n < 1 || b < 0 || b > 6 || b >= n) return hipErrorInvalidValue;
   const int64_t nchunks = int64_t(1) << (n - 1);
   int64_t blocks = (nchunks + kThreads - 1) / kThreads;
-  if (blocks > (int64_t(1) << 22)) blocks = int64_t(1) << 22;
+  if (blocks > kFullGrid) blocks = kFullGrid;
   hipLaunchKernelGGL(k_1q_shuffle, dim3(unsigned(blocks)), dim3(kThreads), 0, st,
                      reinterpret_cast<float4 *>(psi), nchunks, b, m[0], m[1], m[2], m[3]);
   return hipGetLastError();
@@ -531,8 +533,7 @@ hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2
   }
   constexpr int UNR = 1;
   const int64_t nchunks = int64_t(1) << (n - 1);
-  // 2^22 workgroups of 256 stay inside the 2^32 - 1 work-item dispatch limit
-  hipLaunchKernelGGL(k_diag<UNR>, dim3(grid_for(nchunks, kThreads * UNR, 1 << 22)), dim3(kThreads), 0, st,
+  hipLaunchKernelGGL(k_diag<UNR>, dim3(grid_for(nchunks, kThreads * UNR, kFullGrid)), dim3(kThreads), 0, st,
                      reinterpret_cast<float4 *>(psi), nchunks, d_dev, a);
   return hipGetLastError();
 }
@@ -565,13 +566,13 @@ hipError_t launch_swap_bits(float2 *psi, int n, int p, int q, hipStream_t st) {
     q = t;
   }
   const int64_t m = int64_t(1) << (n - 2);
-  hipLaunchKernelGGL(k_swap_bits, dim3(grid_for(m, kThreads, 1 << 22)), dim3(kThreads), 0, st, psi, m, p, q);
+  hipLaunchKernelGGL(k_swap_bits, dim3(grid_for(m, kThreads, kFullGrid)), dim3(kThreads), 0, st, psi, m, p, q);
   return hipGetLastError();
 }
 
 hipError_t launch_probs(const float2 *psi, int n, double *out, int logical, const LayoutArg &L, hipStream_t st) {
   const int64_t dim = int64_t(1) << n;
-  hipLaunchKernelGGL(k_probs, dim3(grid_for(dim, kThreads, 1 << 22)), dim3(kThreads), 0, st, psi, dim, n, out,
+  hipLaunchKernelGGL(k_probs, dim3(grid_for(dim, kThreads, kFullGrid)), dim3(kThreads), 0, st, psi, dim, n, out,
                      logical, L);
   return hipGetLastError();
 }

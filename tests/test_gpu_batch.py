@@ -100,3 +100,19 @@ def test_batch_rejects_bad_input(B):
     bad = [(4, [W.Gate("cnot", (1, 1), W.cnot())])]
     with pytest.raises(SvError):
         B.Batch(bad).allocate().run()
+
+
+def test_batch_prepare_launch_matches_run(B):
+    """Prepared once (records resident), launched twice: identical states and <Z_0> to sv_batch_run."""
+    circs = W.batch_family(48, seed=11, n_lo=8, n_hi=16, d_lo=3, d_hi=9)
+    b = B.Batch(circs).allocate()
+    z_run = b.run()
+    s_run = [b.state(i) for i in range(len(circs))]
+    b.prepare()
+    for _ in range(2):
+        b.states.zero_()
+        z = b.launch()
+        np.testing.assert_array_equal(z, z_run)
+        for i in range(len(circs)):
+            np.testing.assert_array_equal(b.state(i), s_run[i])
+    b.close_prepared()
