@@ -176,7 +176,7 @@ const char *sv_last_error(void);
 /* Where the waves of an MFMA sweep read the gate operand: their own
  * registers (k <= 5), once per workgroup in LDS (k <= 6), or from global
  * memory through the caches (k >= 5; always for k = 7).  AUTO (default)
- * takes the placement measured fastest for each width and precision;
+ * takes the placement measured fastest for each width (LDS up to k = 6);
  * kernels without the requested placement use their AUTO choice. */
 #define SV_OPT_MFMA_OPERAND 6
 #define SV_MFMA_OPERAND_REGS 0

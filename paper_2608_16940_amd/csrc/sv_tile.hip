@@ -140,7 +140,11 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   static_assert(MTT * NCB >= 4 && (MTT * NCB) % 4 == 0, "four waves share the (block, tile) pairs");
   constexpr int MPW = MTT * NCB / 4;     // output tiles per wave
   constexpr bool SHARED_GROUPS = NCB < 4;  // several waves work on the same groups
-  constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * MPW : MPW;
+  // BF16x3 k >= 6: the cross terms hi*lo and lo*hi accumulate apart from
+  // hi*hi (two independent MFMA chains per output tile; 5-10% faster at N=30,
+  // a third set costs occupancy); summed in FP32 before the store
+  constexpr int BSETS = (ALG == ALG_EMBED_BF16X3 && K >= 6) ? 2 : 1;
+  constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * MPW : BSETS * MPW;
   __shared__ float2 lds[TILE];
   __shared__ float opl_s[OPS == OP_LDS ? NOPF : 1];
 
@@ -311,15 +315,19 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
             ah = oph[(mt * KQ + kk) * 64 + lane];
             al = oph[(MTT * KQ + mt * KQ + kk) * 64 + lane];
           }
+          constexpr int XS = (BSETS - 1) * MPW;  // cross-term accumulator offset
           acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[j], 0, 0, 0);
-          acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[j], 0, 0, 0);
-          acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[j], 0, 0, 0);
+          acc[XS + j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[XS + j], 0, 0, 0);
+          acc[XS + j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[XS + j], 0, 0, 0);
         }
       }
       if constexpr (SHARED_GROUPS) __syncthreads();
 #pragma unroll
       for (int j = 0; j < MPW; ++j) {
         const int mt = mt0 + j * MT_STEP;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          for (int t = 1; t < BSETS; ++t) acc[j][r] += acc[t * MPW + j][r];
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[j][2 * e], acc[j][2 * e + 1]);
@@ -646,8 +654,8 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out) {
 hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi, const void *op, hipStream_t st) {
   const bool bf = (prec == SV_PREC_BF16X3);
   int o = opsrc;
-  if (o == SV_MFMA_OPERAND_AUTO)  // measured at N=30 on MI355X: LDS up to k=5 and FP32 k=6, caches beyond
-    o = (tp.K <= 5 || (tp.K == 6 && !bf)) ? SV_MFMA_OPERAND_LDS : SV_MFMA_OPERAND_GLOBAL;
+  if (o == SV_MFMA_OPERAND_AUTO)  // measured at N=30 on MI355X: LDS up to k=6, caches for k=7
+    o = (tp.K <= 6) ? SV_MFMA_OPERAND_LDS : SV_MFMA_OPERAND_GLOBAL;
   switch (tp.K) {
     case 4:
       if (o == SV_MFMA_OPERAND_REGS) return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
