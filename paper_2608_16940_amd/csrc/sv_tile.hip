@@ -112,7 +112,8 @@ struct Scheme {
 // VGPRs; the other k=5 forms would spill at that budget and keep three.
 template <int K, int PREC, int OPS>
 struct WavesPerSimd {
-  static constexpr int value = K <= 4 ? 4 : (K == 5 ? ((PREC == SV_PREC_FP32 && OPS == OP_LDS) ? 4 : 3) : 2);
+  static constexpr int value =
+      K <= 4 ? 4 : (K == 5 ? ((PREC == SV_PREC_FP32 && OPS == OP_LDS) ? 4 : 3) : ((K == 7 && OPS == OP_LDS) ? 1 : 2));
 };
 
 // Register prefetch of the next tile: measured at N=30 on MI355X, FP32 k=6
@@ -654,8 +655,8 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out) {
 hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi, const void *op, hipStream_t st) {
   const bool bf = (prec == SV_PREC_BF16X3);
   int o = opsrc;
-  if (o == SV_MFMA_OPERAND_AUTO)  // measured at N=30 on MI355X: LDS up to k=6, caches for k=7
-    o = (tp.K <= 6) ? SV_MFMA_OPERAND_LDS : SV_MFMA_OPERAND_GLOBAL;
+  if (o == SV_MFMA_OPERAND_AUTO)  // measured at N=30 on MI355X: LDS up to k=6 and FP32 k=7, caches for BF16 k=7
+    o = (tp.K <= 6 || !bf) ? SV_MFMA_OPERAND_LDS : SV_MFMA_OPERAND_GLOBAL;
   switch (tp.K) {
     case 4:
       if (o == SV_MFMA_OPERAND_REGS) return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
@@ -667,7 +668,9 @@ hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi
     case 6:
       if (o == SV_MFMA_OPERAND_LDS) return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
       return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
-    case 7: return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
+    case 7:  // FP32: the two 64 KiB operand planes and the 32 KiB tile fill the 160 KiB of LDS
+      if (!bf && o != SV_MFMA_OPERAND_GLOBAL) return tile_mfma_k<7, 5, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+      return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
     default: return hipErrorInvalidValue;
   }
 }
