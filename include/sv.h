@@ -83,7 +83,10 @@ int sv_reset(sv_state *s);
  * with sv_get_layout.  A matrix whose off-diagonal entries are all exactly
  * zero takes the streaming diagonal lowering (Algorithm 2, diag branch):
  * one pass multiplying each amplitude by the entry its target bits select,
- * layout unchanged.  Unitarity is not checked.
+ * layout unchanged.  A matrix that only permutes the target qubits (entries
+ * exactly 0 and 1, |c> -> |pi(c)> for a permutation of the bits) moves no
+ * data: the layout map absorbs it (SV_VARIANT_AUTO only).  Unitarity is not
+ * checked.
  * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED, SV_ERR_DEVICE.
  */
 int sv_apply_fused(sv_state *s, const double *matrix, const int32_t *targets, int k);
@@ -196,6 +199,7 @@ typedef struct sv_stats {
   int64_t launches;         /* kernels launched by gate and layout calls */
   int64_t by_variant[6];    /* gate applications per SV_VARIANT_* */
   int64_t permute_sweeps;   /* full-sweep tile permutation passes */
+  int64_t layout_only;      /* fused gates that only permute their qubits: applied to the layout map, no sweep */
 } sv_stats;
 int sv_get_stats(const sv_state *s, sv_stats *out);
 

@@ -104,7 +104,9 @@ int sv_plan_free(sv_plan *p);
  * handle's stream with no host work or copy per block, so it can be captured
  * into a HIP graph and replayed (launch-bound circuits: small states, many
  * narrow gates).  Lazy relabel must be off; a run requires the layout map to
- * be the one the plan was bound with.
+ * be the one the plan was bound with, and leaves it as sv_run_plan would
+ * (blocks that only permute qubits go to the layout map, as in
+ * sv_apply_fused), so a second run needs a reset or the original layout.
  *   sv_bound_bytes      device bytes the operands need (*out; 0 if all by value)
  *   sv_plan_bind        lower every block, copy the operands into op_dev
  *                       (caller-owned device memory, >= sv_bound_bytes,

@@ -333,6 +333,33 @@ int launch_lowered(sv_state *s, const Lowered &L, const void *op_dev) {
   return SV_OK;
 }
 
+// True when G maps each basis state |c> to |pi(c)>, pi moving bit j of c to
+// bit perm[j] (a permutation of the block's qubits), with exact 0/1 entries.
+bool qubit_permutation(const double *G, int k, int *perm) {
+  const int D = 1 << k;
+  for (int i = 0; i < D * D; ++i)
+    if (G[2 * i + 1] != 0.0 || (G[2 * i] != 0.0 && G[2 * i] != 1.0)) return false;
+  int used = 0;
+  for (int j = 0; j < k; ++j) {
+    int row = -1;
+    for (int r = 0; r < D; ++r)
+      if (G[2 * (r * D + (1 << j))] == 1.0) {
+        if (row >= 0) return false;
+        row = r;
+      }
+    if (row <= 0 || (row & (row - 1)) || (used & row)) return false;
+    used |= row;
+    perm[j] = __builtin_ctz(unsigned(row));
+  }
+  for (int c = 0; c < D; ++c) {
+    int r = 0;
+    for (int j = 0; j < k; ++j) r |= ((c >> j) & 1) << perm[j];
+    for (int rr = 0; rr < D; ++rr)
+      if (G[2 * (rr * D + c)] != (rr == r ? 1.0 : 0.0)) return false;
+  }
+  return true;
+}
+
 int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
   Lowered L;
   int rc = lower(s, matrix, A, k, true, &L);
@@ -466,6 +493,23 @@ int sv_apply_fused(sv_state *s, const double *matrix, const int32_t *targets, in
         return SV_ERR_ARG;
       }
     A[j] = s->L[targets[j]];
+  }
+  // A block that only permutes its qubits (a SWAP network) moves no data: the
+  // value of logical qubit targets[j] now sits under targets[perm[j]], which
+  // the layout map records (Lemma 2 per exchanged pair): L'(targets[perm[j]])
+  // = L(targets[j]).  Forced variants still sweep.
+  int perm[SV_MAX_K];
+  if (s->variant == SV_VARIANT_AUTO && qubit_permutation(matrix, k, perm)) {
+    int32_t old[SV_MAX_K];
+    for (int j = 0; j < k; ++j) old[j] = s->L[targets[j]];
+    for (int j = 0; j < k; ++j) {
+      s->L[targets[perm[j]]] = old[j];
+      s->Linv[old[j]] = targets[perm[j]];
+    }
+    s->stats.layout_only += 1;
+    ++s->clock;
+    for (int j = 0; j < k; ++j) s->last_use[targets[j]] = s->clock;
+    return SV_OK;
   }
   const int rc = apply_physical(s, matrix, A, k);
   if (rc == SV_OK) {
@@ -794,10 +838,11 @@ int sv_get_stats(const sv_state *s, sv_stats *out) {
 // ------------------------------------------------------------------ bound plans
 struct sv_bound {
   sv_state *s = nullptr;
-  std::vector<Lowered> ops;
-  std::vector<size_t> off;  // operand offset in op_dev (SIZE_MAX: by value)
+  std::vector<Lowered> ops;  // variant -1: a qubit permutation, absorbed by the layout map
+  std::vector<size_t> off;   // operand offset in op_dev (SIZE_MAX: by value)
   char *op_dev = nullptr;
-  int32_t L[64];
+  int32_t L[64];             // layout a run starts from
+  int32_t Lend[64];          // layout a run leaves (after the absorbed permutations)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;  // private stream the graph is captured on
@@ -806,7 +851,8 @@ struct sv_bound {
 
 namespace {
 
-int lower_plan(sv_state *s, const sv_plan *p, std::vector<Lowered> *ops, std::vector<size_t> *off, size_t *bytes) {
+int lower_plan(sv_state *s, const sv_plan *p, std::vector<Lowered> *ops, std::vector<size_t> *off, size_t *bytes,
+               int32_t *Lend) {
   if (s->lazy) {
     set_error("bound plans need lazy relabel off");
     return SV_ERR_ARG;
@@ -817,6 +863,8 @@ int lower_plan(sv_state *s, const sv_plan *p, std::vector<Lowered> *ops, std::ve
   ops->assign(static_cast<size_t>(nb), Lowered());
   off->assign(static_cast<size_t>(nb), SIZE_MAX);
   size_t total = 0;
+  int32_t L[64];  // the layout as the run will see it block by block
+  std::memcpy(L, s->L, sizeof(L));
   for (int i = 0; i < nb; ++i) {
     int k = 0, ng = 0, dg = 0;
     int32_t t[8];
@@ -831,7 +879,15 @@ int lower_plan(sv_state *s, const sv_plan *p, std::vector<Lowered> *ops, std::ve
         set_error("plan target outside the state");
         return SV_ERR_ARG;
       }
-      A[j] = s->L[t[j]];
+      A[j] = L[t[j]];
+    }
+    int perm[SV_MAX_K];
+    if (s->variant == SV_VARIANT_AUTO && qubit_permutation(m.data(), k, perm)) {  // as sv_apply_fused
+      int32_t old[SV_MAX_K];
+      for (int j = 0; j < k; ++j) old[j] = L[t[j]];
+      for (int j = 0; j < k; ++j) L[t[perm[j]]] = old[j];
+      (*ops)[size_t(i)].variant = -1;
+      continue;
     }
     rc = lower(s, m.data(), A, k, false, &(*ops)[size_t(i)]);
     if (rc) return rc;
@@ -841,6 +897,7 @@ int lower_plan(sv_state *s, const sv_plan *p, std::vector<Lowered> *ops, std::ve
     }
   }
   *bytes = total;
+  if (Lend) std::memcpy(Lend, L, sizeof(L));
   return SV_OK;
 }
 
@@ -858,6 +915,7 @@ int bound_check(const sv_bound *b) {
 
 int bound_launch_all(sv_bound *b) {
   for (size_t i = 0; i < b->ops.size(); ++i) {
+    if (b->ops[i].variant < 0) continue;
     const void *dev = b->off[i] == SIZE_MAX ? nullptr : b->op_dev + b->off[i];
     const int rc = launch_lowered(b->s, b->ops[i], dev);
     if (rc) return rc;
@@ -868,7 +926,17 @@ int bound_launch_all(sv_bound *b) {
 void add_stats(sv_stats *a, const sv_stats &d) {
   a->gate_sweeps += d.gate_sweeps;
   a->launches += d.launches;
+  a->layout_only += d.layout_only;
   for (int v = 0; v < 6; ++v) a->by_variant[v] += d.by_variant[v];
+}
+
+// After a run: the handle's layout is the one the absorbed permutations leave.
+void bound_finish(sv_bound *b) {
+  sv_state *s = b->s;
+  for (int q = 0; q < s->n; ++q) {
+    s->L[q] = b->Lend[q];
+    s->Linv[b->Lend[q]] = q;
+  }
 }
 
 }  // namespace
@@ -882,7 +950,7 @@ int sv_bound_bytes(sv_state *s, const sv_plan *p, size_t *out) {
   }
   std::vector<Lowered> ops;
   std::vector<size_t> off;
-  return lower_plan(s, p, &ops, &off, out);
+  return lower_plan(s, p, &ops, &off, out, nullptr);
 }
 
 int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, sv_bound **out) {
@@ -893,7 +961,7 @@ int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, s
   sv_bound *b = new sv_bound();
   b->s = s;
   size_t need = 0;
-  int rc = lower_plan(s, p, &b->ops, &b->off, &need);
+  int rc = lower_plan(s, p, &b->ops, &b->off, &need, b->Lend);
   if (rc) {
     delete b;
     return rc;
@@ -923,18 +991,27 @@ int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, s
   std::memcpy(b->L, s->L, sizeof(b->L));
   std::memset(&b->per_run, 0, sizeof(b->per_run));
   for (const Lowered &L : b->ops) {
+    if (L.variant < 0) {
+      b->per_run.layout_only += 1;
+      continue;
+    }
     b->per_run.gate_sweeps += 1;
     b->per_run.launches += 1;
-    if (L.variant >= 0 && L.variant < 6) b->per_run.by_variant[L.variant] += 1;
+    if (L.variant < 6) b->per_run.by_variant[L.variant] += 1;
   }
   *out = b;
   return SV_OK;
 }
 
 int sv_bound_run(sv_bound *b) {
-  const int rc = bound_check(b);
+  int rc = bound_check(b);
   if (rc) return rc;
-  return bound_launch_all(b);
+  const int64_t before = b->s->stats.layout_only;
+  rc = bound_launch_all(b);
+  if (rc) return rc;
+  b->s->stats.layout_only = before + b->per_run.layout_only;
+  bound_finish(b);
+  return SV_OK;
 }
 
 int sv_bound_graph_run(sv_bound *b) {
@@ -983,6 +1060,7 @@ int sv_bound_graph_run(sv_bound *b) {
     return SV_ERR_DEVICE;
   }
   add_stats(&s->stats, b->per_run);
+  bound_finish(b);
   return SV_OK;
 }
 

@@ -220,7 +220,9 @@ def test_greedy_plan_brickwork_plus_qft(P, n, k_max):
     plan = P.Plan.greedy(n, gates, k_max)
     plan.run(sv)
     check_close(ref, gpu_logical(sv), what=("plan", n, k_max))
-    assert sv.stats()["gate_sweeps"] == len(plan)
+    st = sv.stats()
+    assert st["gate_sweeps"] + st["layout_only"] == len(plan)
+    assert st["layout_only"] >= 1  # the QFT's closing swaps need no sweep
 
 
 def test_ghz_and_qft_closed_forms(P):
@@ -396,7 +398,8 @@ def test_bound_plan_and_graph_replays(P, prec):
         np.testing.assert_array_equal(got, ref)
         assert abs(sv.norm() - 1) < 2e-4  # eager work between replays
         sv.sample(rep, 100)
-    assert sv.stats()["gate_sweeps"] == len(plan)  # counters restart at each reset; a replay adds one run
+    st = sv.stats()  # counters restart at each reset; a replay adds one run
+    assert st["gate_sweeps"] + st["layout_only"] == len(plan) and st["layout_only"] >= 1
     if prec == "fp32":
         check_close(oracle.run(n, gates), oracle.decode(ref, sv.layout()), what="bound plan")
     bound.close()
@@ -423,4 +426,43 @@ def test_bound_plan_guards(P):
     with pytest.raises(RuntimeError):
         bound.run_graph()
     bound.close()
+    sv.close()
+
+
+def perm_matrix(k, perm):
+    """|c> -> |pi(c)>, bit j of c moving to bit perm[j]."""
+    d = 1 << k
+    m = np.zeros((d, d), dtype=np.complex128)
+    for c in range(d):
+        r = sum(((c >> j) & 1) << perm[j] for j in range(k))
+        m[r, c] = 1
+    return m
+
+
+def test_qubit_permutations_go_to_the_layout_map(P):
+    """Blocks that only permute their qubits move no data: the layout map absorbs them."""
+    n = 12
+    rng = np.random.default_rng(17)
+    gates = rand_state_gates(n, rng, 1)
+    swaps = [W.Gate("swap", (2, 9), perm_matrix(2, [1, 0])),
+             W.Gate("cyc", (0, 5, 11), perm_matrix(3, [1, 2, 0])),
+             W.Gate("net", (1, 3, 7, 10), perm_matrix(4, [3, 2, 1, 0])),
+             W.Gate("id", (4, 6), np.eye(4, dtype=np.complex128)),
+             W.random_dense(n, 2, rng, (9, 2))]
+    gates += swaps
+    ref = oracle.run(n, gates)
+    sv = P.StateVector(n)
+    sv.apply_gates(gates[:-len(swaps)])
+    before = sv.stats()
+    sv.apply_gates(swaps)
+    after = sv.stats()
+    assert after["layout_only"] - before["layout_only"] == 4
+    assert after["gate_sweeps"] - before["gate_sweeps"] == 1
+    assert list(sv.layout()) != list(range(n))
+    check_close(ref, gpu_logical(sv), what="layout-only permutations")
+    # a forced variant still sweeps
+    sv.set_variant("valu")
+    s0 = sv.stats()["gate_sweeps"]
+    sv.apply(perm_matrix(2, [1, 0]), [2, 9])
+    assert sv.stats()["gate_sweeps"] == s0 + 1
     sv.close()
