@@ -9,11 +9,13 @@ through the C-ABI, then 1000 shots sampled and decoded through the final
 layout map.
 
 Prints one JSON line.  ``value`` = fused gate-sweeps per second over whole
-steps (init + all sweeps + sampling).  ``roofline`` reports the dominant
-kernel (the k=5 MFMA sweep) from HIP events recorded around each of its
-launches inside the timed region, against the 8 TB/s HBM peak.
-``cpu_baseline`` times the CPU oracle on a bounded prefix of the same
-circuit on this host's cores.
+steps (init + all sweeps + sampling), counting the sweeps that ran (blocks
+that only permute qubits go to the layout map and run none).  ``roofline``
+reports the kernel with the largest share of the step, timed by HIP events
+recorded around every launch inside the timed region, against the 8 TB/s
+HBM peak; ``kernels`` lists every kernel class.  ``cpu_baseline`` times the
+CPU oracle on a bounded prefix of the same circuit on this host's cores.
+Other workloads (``--workload``): learned, batch, precision, c1.
 """
 import argparse
 import hashlib
