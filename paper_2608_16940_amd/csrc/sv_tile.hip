@@ -176,8 +176,19 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   float ra[NREG];
   (void)ra;
   if constexpr (OPS == OP_REG) {
+    if constexpr (ALG == ALG_EMBED_BF16X3) {
+      // the bf16 operand holds one 8-byte group of four per lane: floats (2i, 2i + 1) of this lane
+      const float2 *op2 = reinterpret_cast<const float2 *>(a.op);
 #pragma unroll
-    for (int i = 0; i < NREG; ++i) ra[i] = opf[i * 64 + lane];
+      for (int i = 0; i < NREG / 2; ++i) {
+        const float2 t = op2[i * 64 + lane];
+        ra[2 * i] = t.x;
+        ra[2 * i + 1] = t.y;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) ra[i] = opf[i * 64 + lane];
+    }
   } else if constexpr (OPS == OP_LDS) {
     const float4 *src = reinterpret_cast<const float4 *>(a.op);
     float4 *dst = reinterpret_cast<float4 *>(opl_s);
@@ -665,10 +676,11 @@ hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi
       if (o == SV_MFMA_OPERAND_REGS) return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
       if (o == SV_MFMA_OPERAND_GLOBAL) return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
       return bf ? tile_mfma_k<5, 7, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<5, 7, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
-    case 6:
-      if (o == SV_MFMA_OPERAND_LDS) return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+    case 6:  // no register form: REGS takes the automatic choice (LDS)
+      if (o != SV_MFMA_OPERAND_GLOBAL) return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
       return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
-    case 7:  // FP32: the two 64 KiB operand planes and the 32 KiB tile fill the 160 KiB of LDS
+    case 7:  // FP32: the two 64 KiB operand planes and the 32 KiB tile fill the 160 KiB of LDS;
+             // BF16x3 (256 KiB operand) always reads through the caches; REGS takes the automatic choice
       if (!bf && o != SV_MFMA_OPERAND_GLOBAL) return tile_mfma_k<7, 5, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
       return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
     default: return hipErrorInvalidValue;

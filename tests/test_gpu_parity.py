@@ -466,3 +466,24 @@ def test_qubit_permutations_go_to_the_layout_map(P):
     sv.apply(perm_matrix(2, [1, 0]), [2, 9])
     assert sv.stats()["gate_sweeps"] == s0 + 1
     sv.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 2e-4)])
+def test_every_mfma_operand_placement(P, prec, tol):
+    """Each MFMA sweep instance (operand in registers, LDS or read through the caches; k = 4..7)."""
+    n = 14
+    rng = np.random.default_rng(31)
+    prep = rand_state_gates(n, rng, 1)
+    for opsrc in ("regs", "lds", "global", "auto"):
+        gates = prep + [W.random_dense(n, k, rng) for k in (4, 5, 6, 7)]
+        ref = oracle.run(n, gates)
+        sv = P.StateVector(n)
+        sv.apply_gates(prep)
+        sv.set_precision(prec)
+        sv.set_variant("mfma")
+        sv.set_option(P._native.OPT_MFMA_OPERAND, P._native.MFMA_OPERAND[opsrc])
+        sv.apply_gates(gates[len(prep):])
+        m = oracle.metrics(ref, gpu_logical(sv))
+        say("operand", opsrc, prec, m["rel_l2"])
+        assert m["infidelity"] <= 1e-5 and m["max_abs"] <= 1e-5 and m["rel_l2"] <= tol, (opsrc, m)
+        sv.close()
