@@ -499,6 +499,44 @@ def bench_precision(args):
                 "alg_TFLOPs": alg / s_run / 1e12, "mfma_TFLOPs": ex / s_run / 1e12,
                 "mfma_frac_of_peak": ex / s_run / 1e12 / peak[prec]}
             log("bench precision: k<=%d %s %.3f s per circuit (%d blocks)" % (kcap, prec, s_run, len(blocks)))
+    sv.close()
+    # fidelity per result at N=28 (the same generator, seed and depth): sampled
+    # amplitudes against the complex128 oracle values committed in tests/golden
+    fidelity = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "brickwork_n28_amplitudes.txt")
+    if args.seed == 0 and os.path.exists(gpath):
+        gi, gv = [], []
+        with open(gpath) as f:
+            for ln in f:
+                if ln.startswith("#") or not ln.strip():
+                    continue
+                i, re_, im_ = ln.split()
+                gi.append(int(i))
+                gv.append(complex(float(re_), float(im_)))
+        gi = np.array(gi, dtype=np.int64)
+        gv = np.array(gv, dtype=np.complex128)
+        g28 = W.brickwork(28, depth, 0)
+        s28 = P.StateVector(28, device="cuda:0")
+        for kcap in (6, 7):
+            plan = P.Plan.greedy(28, g28, kcap)
+            for prec in ("fp32", "bf16x3"):
+                s28.set_precision(prec)
+                s28.reset()
+                plan.run(s28)
+                lay = s28.layout()
+                phys = np.zeros_like(gi)
+                for q, pos in enumerate(lay):
+                    phys |= ((gi >> q) & 1) << int(pos)
+                s28.sync()
+                got = s28.amps[torch.from_numpy(phys).to(s28.amps.device)].cpu().numpy().astype(np.complex128)
+                ov = np.vdot(gv, got)
+                fid = abs(ov) ** 2 / (np.vdot(gv, gv).real * np.vdot(got, got).real)
+                fidelity["n28_k%d_%s" % (kcap, prec)] = {
+                    "one_minus_fidelity_sampled": 1 - fid, "max_abs_diff": float(np.abs(got - gv).max()),
+                    "rel_l2_sampled": float(np.linalg.norm(got - gv) / np.linalg.norm(gv)),
+                    "norm_minus_1": s28.norm() - 1, "samples": int(gi.size)}
+        s28.close()
+    sv = P.StateVector(n, device="cuda:0")
     # single sweeps of random dense gates on random targets
     rng = np.random.default_rng(args.seed)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -528,7 +566,7 @@ def bench_precision(args):
         "n_gpus": 1, "higher_is_better": False, "dtype": "fp32 / bf16x3 (fp32 accumulate)", "data": "synthetic",
         "config": {"workload": "brickwork depth %d (Haar SU(2) + CZ, seed %d), N=%d complex64, greedy fusion"
                                % (depth, args.seed, n)},
-        "circuits": circuits, "single_sweeps": rows,
+        "circuits": circuits, "single_sweeps": rows, "fidelity_vs_oracle_n28": fidelity,
         "roofline": {"bound": "mfma", "kernel": "k_tile_mfma<K=7> fp32 (Gauss)",
                      "achieved": k7["mfma_frac_of_peak"] * peak["fp32"], "peak": peak["fp32"],
                      "unit": "TFLOP/s", "frac": k7["mfma_frac_of_peak"], "traffic": None},
