@@ -24,6 +24,22 @@ __device__ __forceinline__ int64_t insert_zero_bit(int64_t x, int p) {
   return ((x >> p) << (p + 1)) | low;
 }
 
+// Streaming order.  Work item `lin` (one 16-byte chunk per thread) is moved
+// to chunk stream_chunk(lin): within each aligned block of 2^14 chunks the
+// six low workgroup bits go to chunk bits 6..11 and the two wave bits to
+// bits 12..13, so 64 consecutive workgroups interleave at 1 KiB granularity
+// and a workgroup's waves sit 64 KiB apart.  A bijection that keeps the lane
+// bits; measured on MI355X at N=30 it raises an in-place streaming pass from
+// 6.1 to 6.8 TB/s (sequential order leaves HBM channels unevenly loaded).
+// It is an HBM effect: work sets below 2^24 items (states that stay in the
+// caches) keep the plain order.  Used by every kernel whose work items are
+// independent chunks, amplitudes or groups.
+__device__ __forceinline__ int64_t stream_chunk(int64_t lin, int64_t nchunks) {
+  if (nchunks < (int64_t(1) << 24)) return lin;
+  const int64_t lane = lin & 63, wave = (lin >> 6) & 3, blk = (lin >> 8) & 63;
+  return (lin & ~int64_t(16383)) | (wave << 12) | (blk << 6) | lane;
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -51,7 +67,8 @@ inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 20) {
 __global__ __launch_bounds__(kThreads) void k_init_zero(float4 *psi4, int64_t n4, float2 *psi) {
   const int64_t stride = int64_t(gridDim.x) * kThreads;
   for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n4; i += stride)
-    psi4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    psi4[stream_chunk(i, n4)] = make_float4(0.f, 0.f, 0.f, 0.f);
+  // chunk 0 was zeroed by this same thread (item 0 maps to chunk 0)
   if (blockIdx.x == 0 && threadIdx.x == 0) psi[0] = make_float2(1.f, 0.f);
 }
 
@@ -76,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_valu(float2 *__restrict__ ps
   constexpr int D = 1 << K;
   const int64_t stride = int64_t(gridDim.x) * kThreads;
   for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < ngroups; g += stride) {
-    int64_t base = g;
+    int64_t base = stream_chunk(g, ngroups);
 #pragma unroll
     for (int j = 0; j < K; ++j) base = insert_zero_bit(base, a.sorted[j]);
     float2 in[D];
@@ -105,7 +122,9 @@ __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ ps
   for (int64_t blk = int64_t(blockIdx.x) * kThreads; blk < nchunks; blk += int64_t(gridDim.x) * kThreads) {
     const int64_t t = blk + threadIdx.x;
     const bool active = t < nchunks;
-    float4 v = active ? psi4[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // the streaming order keeps lane bits: partners (bits 1..6) stay in the wave
+    const int64_t c = active ? stream_chunk(t, nchunks) : 0;
+    float4 v = active ? psi4[c] : make_float4(0.f, 0.f, 0.f, 0.f);
     float2 a0 = make_float2(v.x, v.y), a1 = make_float2(v.z, v.w);
     float2 o0, o1;
     if (b == 0) {
@@ -127,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ ps
         o1 = cfma(m01, p1, cmul(m00, a1));
       }
     }
-    if (active) psi4[t] = make_float4(o0.x, o0.y, o1.x, o1.y);
+    if (active) psi4[c] = make_float4(o0.x, o0.y, o1.x, o1.y);
   }
 }
 
@@ -136,10 +155,9 @@ __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ ps
 // r(y) is physical bit A_j of y, and leaves the layout unchanged (the diag
 // branch of the lazy-TTGT lowering, Eq. cost-diag-formal: one streaming pass
 // whatever the target positions).  Each thread takes UNR 16-byte chunks (two
-// amplitudes that differ in physical bit 0); the 2^k table sits in LDS.  One
-// chunk per thread over a full grid streams fastest on MI355X (6.1 TB/s in
-// place at N=30, against 5.5 TB/s for four chunks per thread on a capped,
-// grid-strided launch).
+// amplitudes that differ in physical bit 0), in the streaming order of
+// stream_chunk; the 2^k table sits in LDS.  One chunk per thread over a full
+// grid (four per thread on a capped, grid-strided launch was 10% slower).
 constexpr int kDiagByValue = 16;  // tables up to k = 4 travel in the kernel arguments
 struct DiagArgs {
   int k;
@@ -157,14 +175,16 @@ __global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, in
   const int64_t step = int64_t(gridDim.x) * kThreads * UNR;
   for (int64_t c0 = int64_t(blockIdx.x) * kThreads * UNR + threadIdx.x; c0 < nchunks; c0 += step) {
     floatx4 v[UNR];
+    int64_t cc[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int64_t c = c0 + int64_t(u) * kThreads;
-      if (c < nchunks) v[u] = __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(psi4 + c));
+      const int64_t lin = c0 + int64_t(u) * kThreads;
+      cc[u] = lin < nchunks ? stream_chunk(lin, nchunks) : nchunks;
+      if (cc[u] < nchunks) v[u] = __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(psi4 + cc[u]));
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int64_t c = c0 + int64_t(u) * kThreads;
+      const int64_t c = cc[u];
       if (c >= nchunks) continue;
       const int64_t y = c << 1;  // first amplitude of the chunk; physical bit 0 is clear
       int r = 0;
@@ -248,7 +268,8 @@ __device__ __forceinline__ uint64_t physical_to_logical(uint64_t y, int n, const
 __global__ __launch_bounds__(kThreads) void k_probs(const float2 *__restrict__ psi, int64_t dim, int n,
                                                     double *__restrict__ out, int logical, LayoutArg L) {
   const int64_t stride = int64_t(gridDim.x) * kThreads;
-  for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < dim; x += stride) {
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < dim; i += stride) {
+    const int64_t x = stream_chunk(i, dim);
     const int64_t y = logical ? logical_to_physical(x, n, L) : x;
     out[x] = prob_of(psi[y]);
   }

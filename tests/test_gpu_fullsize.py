@@ -149,3 +149,29 @@ def test_largest_states_dispatch_limits(P, n):
     sv.close()
     del sv
     torch.cuda.empty_cache()
+
+
+def test_probs_large_state_exact(P):
+    """FP64 probabilities at N=26 (the large-state streaming order), physical and logical."""
+    import torch
+    n = 26
+    rng = np.random.default_rng(26)
+    sv = P.StateVector(n)
+    for q in (0, 3, 9, 17, 25):
+        sv.apply(W.haar_su2(rng), [q])
+    sv.apply(W.cnot(), [3, 24])
+    layout = list(range(n))
+    layout[1], layout[20] = layout[20], layout[1]
+    sv.permute_layout(layout)
+    a = sv.amps
+    want = a.real.double() ** 2 + a.imag.double() ** 2
+    p_phys = sv.probs(logical=False)
+    assert torch.equal(p_phys, want)
+    p_log = sv.probs(logical=True)
+    idx = torch.arange(1 << n, device=a.device, dtype=torch.int64)
+    phys = torch.zeros_like(idx)
+    for q, pos in enumerate(sv.layout()):
+        phys |= ((idx >> q) & 1) << int(pos)
+    assert torch.equal(p_log, want[phys])
+    assert abs(float(p_phys.sum()) - 1) < 1e-5
+    sv.close()
