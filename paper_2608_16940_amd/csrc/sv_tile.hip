@@ -579,8 +579,20 @@ bool make_gate_tile(int n, int K, const int32_t *A, uint64_t extra, TilePlan *tp
   uint64_t lowmask = extra;
   int got = __builtin_popcountll(extra);
   if (got > M) return false;
-  for (int p = 0; p < n && got < M; ++p)
+  // Workgroups are handed to the eight XCDs in turn, so the three lowest
+  // tile-index bits pick the XCD.  Leaving the three lowest non-target bits
+  // from bit 7 up out of the tile puts them there: each XCD then takes 1 KiB
+  // pieces spread over every 8 KiB when the targets allow it.  Measured at
+  // N=30: k=4 on bits 0-3 2.84 -> 2.61 ms, k=5 1-5% faster, no pattern slower.
+  uint64_t reserve = 0;
+  for (int p = 7, r = 0; p < n && r < 3; ++p)
     if (!((tmask >> p) & 1) && !((lowmask >> p) & 1)) {
+      reserve |= uint64_t(1) << p;
+      ++r;
+    }
+  if (n - K - __builtin_popcountll(reserve) < M) reserve = 0;
+  for (int p = 0; p < n && got < M; ++p)
+    if (!((tmask >> p) & 1) && !((lowmask >> p) & 1) && !((reserve >> p) & 1)) {
       lowmask |= uint64_t(1) << p;
       ++got;
     }
