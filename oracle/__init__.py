@@ -20,7 +20,7 @@ in numpy:
   the left (Section IV-C);
 * ``mlp_*`` -- FP64 forward, backward and Adam step for the cost model.
 
-Parity status of each function is listed in the design doc; every function here is
+Every function here is
 pinned by a ``-m "not gpu"`` test in ``tests/test_oracle.py``.
 """
 from __future__ import annotations

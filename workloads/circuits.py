@@ -9,7 +9,7 @@ row and column index).
 
 Families (stand-ins for the paper's random-brickwork ``rand{N}x50``,
 ``qft{N}`` and depth-20 weak-scaling inputs of Section V-A, whose files are
-not available; shapes follow the workload definitions listed in the design doc):
+not available; the shapes, sizes and seeds follow the paper's workloads):
 
 * brickwork(n, depth, seed): each layer applies a Haar-random SU(2) to every
   qubit, then CZ on neighbour pairs (2i, 2i+1) on even layers and
