@@ -13,7 +13,7 @@ import numpy as np
 from . import _native
 from ._native import SvError, check, lib  # noqa: F401
 
-__all__ = ["StateVector", "sample_probs", "workspace_bytes", "SvError"]
+__all__ = ["StateVector", "DensityMatrix", "sample_probs", "workspace_bytes", "SvError"]
 
 
 def _torch():
@@ -305,3 +305,6 @@ class BoundPlan:
             self.close()
         except Exception:
             pass
+
+
+from .density import DensityMatrix, SuperGate, superop, superop_gates  # noqa: E402,F401

@@ -1,8 +1,7 @@
 """ctypes binding of libsv.so (argument marshalling only).
 
-Every function here forwards to the C-ABI declared in ``include/sv.h`` and
-``include/sv_plan.h``.  There is no fallback: if the library has not been
-built, loading fails loudly.
+Every function here forwards to the C-ABI declared in ``include/*.h``.  There
+is no fallback: if the library has not been built, loading fails loudly.
 """
 from __future__ import annotations
 
@@ -74,6 +73,16 @@ SIGNATURES = [
     ("sv_sample_probs", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, _u64p, _vp,
                                        ctypes.c_size_t, _vp]),
     ("sv_sync", ctypes.c_int, [_vp]),
+    ("sv_dm_state_bytes", ctypes.c_size_t, [ctypes.c_int]),
+    ("sv_dm_workspace_bytes", ctypes.c_size_t, [ctypes.c_int]),
+    ("sv_dm_alloc", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t,
+                                   _vp]),
+    ("sv_dm_qubits", ctypes.c_int, [_vp]),
+    ("sv_dm_superop", ctypes.c_int, [_dp, ctypes.c_int, ctypes.c_int, _dp]),
+    ("sv_dm_apply_channel", ctypes.c_int, [_vp, _dp, ctypes.c_int, _i32p, ctypes.c_int]),
+    ("sv_dm_probs", ctypes.c_int, [_vp, _vp]),
+    ("sv_dm_trace", ctypes.c_int, [_vp, _dp]),
+    ("sv_dm_sample", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int64, _u64p, _vp]),
     ("sv_last_error", ctypes.c_char_p, []),
     ("sv_set_option", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     ("sv_get_option", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),

@@ -52,35 +52,7 @@ size_t workspace_layout(int n, char *base, Workspace *ws) {
 
 using namespace sv;
 
-struct sv_state {
-  int n = 0;
-  float2 *amps = nullptr;
-  char *ws_base = nullptr;
-  size_t ws_bytes = 0;
-  Workspace ws;
-  hipStream_t st = nullptr;
-  int32_t L[64];
-  int32_t Linv[64];
-  // options
-  int variant = SV_VARIANT_AUTO;
-  int prec = SV_PREC_FP32;
-  int mfma_min_k = 4;
-  int lazy = 0;
-  int low_bits = 12;
-  int policy = SV_POLICY_BELADY;
-  int opsrc = SV_MFMA_OPERAND_AUTO;
-  // relabel policy state: planner hints and recency per logical qubit
-  bool have_hints = false;
-  int64_t next_use[64];
-  int64_t last_use[64];
-  int64_t clock = 0;
-  // operand staging ring
-  char *pinned = nullptr;
-  hipEvent_t ev[kRingSlots];
-  bool ev_live[kRingSlots];
-  int ring_next = 0;
-  sv_stats stats;
-};
+
 
 namespace {
 

@@ -103,7 +103,8 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out);
 
 // Tile geometry for a dense gate on physical targets A (gate order).  The
 // non-target tile bits are the bits of `extra` (which must not contain targets)
-// followed by the lowest other non-target bits, M in total.  Returns false if
+// followed by the lowest other non-target bits, M in total, except that up to
+// three non-target bits from bit 7 up are left to the tile index.  Returns false if
 // the state is too small for the MFMA tiling.
 bool make_gate_tile(int n, int K, const int32_t *A, uint64_t extra, TilePlan *tp);
 int mfma_tile_M(int K);
@@ -116,3 +117,35 @@ hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi
 hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st);
 
 }  // namespace sv
+
+// The state handle behind the C-ABI's opaque sv_state (one per state vector).
+struct sv_state {
+  int n = 0;
+  int dm_n = 0;  // density-matrix handle: N of the 2N-qubit vectorised state, else 0
+  float2 *amps = nullptr;
+  char *ws_base = nullptr;
+  size_t ws_bytes = 0;
+  sv::Workspace ws;
+  hipStream_t st = nullptr;
+  int32_t L[64];
+  int32_t Linv[64];
+  // options
+  int variant = SV_VARIANT_AUTO;
+  int prec = SV_PREC_FP32;
+  int mfma_min_k = 4;
+  int lazy = 0;
+  int low_bits = 12;
+  int policy = SV_POLICY_BELADY;
+  int opsrc = SV_MFMA_OPERAND_AUTO;
+  // relabel policy state: planner hints and recency per logical qubit
+  bool have_hints = false;
+  int64_t next_use[64];
+  int64_t last_use[64];
+  int64_t clock = 0;
+  // operand staging ring
+  char *pinned = nullptr;
+  hipEvent_t ev[sv::kRingSlots];
+  bool ev_live[sv::kRingSlots];
+  int ring_next = 0;
+  sv_stats stats;
+};
