@@ -5,6 +5,8 @@ test replays the records exactly as the kernel does — gather each slice of
 14 qubits, apply the pass's gates in slice coordinates, scatter back — in
 complex128 numpy, and compares with the oracle applying the original gates.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -111,3 +113,28 @@ def test_records_replay_equals_oracle(B, n, depth, reverse):
         assert 1 <= passes <= len(ops)
     else:
         assert passes == 0
+
+
+def test_committed_batch_golden_matches_oracle():
+    """The committed sample (written by tests/golden/make_batch_golden.py) equals the oracle now."""
+    import oracle
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch4096_seed0_sample.txt")
+    circ, amps = {}, {}
+    with open(path) as f:
+        for ln in f:
+            w = ln.split()
+            if not w or w[0].startswith("#"):
+                continue
+            if w[0] == "circ":
+                circ[int(w[1])] = (int(w[2]), float(w[3]))
+            else:
+                amps.setdefault(int(w[1]), []).append((int(w[2]), complex(float(w[3]), float(w[4]))))
+    assert len(circ) == 64 and all(len(v) == 16 for v in amps.values())
+    circs = W.batch_family(65, seed=0)  # circuit i depends only on (seed, i)
+    for i in (0, 64):
+        n, gates = circs[i]
+        assert n == circ[i][0]
+        psi = oracle.run(n, gates)
+        assert abs(oracle.expect_z(psi, 0) - circ[i][1]) < 1e-14
+        for x, v in amps[i]:
+            assert abs(psi[x] - v) < 1e-15
