@@ -652,9 +652,10 @@ def bench_density(args):
 
     Each layer: Haar SU(2) on every qubit, CZ on neighbour pairs, a two-qubit
     depolarizing channel (p = 1e-3) after every CZ.  Channels become
-    superoperators on (V, V + N) and are fused by the greedy planner over the
-    2N vector qubits.  A step: |0><0|, every fused sweep, then shots drawn
-    from the diagonal.  Parity of this path is covered by the GPU tests; the
+    superoperators on (V, V + N); the learned planner fuses them over the 2N
+    vector qubits (greedy k <= 6 and the paper's pipeline are timed beside
+    it).  A step: |0><0|, every fused sweep, then shots drawn from the
+    diagonal.  Parity of this path is covered by the GPU tests; the
     dense-matrix oracle cannot run N=15 (16 GiB matrices, 2^46 flops per
     Kraus operator), so there is no CPU baseline here.
     """
@@ -662,23 +663,24 @@ def bench_density(args):
     import torch
 
     import paper_2608_16940_amd as P
+    from paper_2608_16940_amd import costmodel as C
     from workloads import noise as Nz
 
     rows = args.n if args.n != 30 else 15
     depth = args.depth if args.depth != 24 else 8
-    kmax = args.kmax if args.kmax != 5 else 6
     chans = Nz.noisy_brickwork(rows, depth, 1e-3, args.seed)
+    params, _ = C.load()
     t0 = time.perf_counter()
     gates = P.superop_gates(rows, chans)
-    plan = P.Plan.greedy(2 * rows, gates, kmax)
+    plan = P.Plan.learned(2 * rows, gates, params)
     blocks = plan.blocks()
     plan_s = time.perf_counter() - t0
     classes = [kernel_class(b, 2 * rows) for b in blocks]
     kcount = {}
     for b in blocks:
         kcount[str(b["k"])] = kcount.get(str(b["k"]), 0) + 1
-    log("bench density: N=%d channels=%d blocks=%d by_k=%s plan+superops %.2f s" % (rows, len(chans), len(blocks),
-                                                                                  kcount, plan_s))
+    log("bench density: N=%d channels=%d learned blocks=%d by_k=%s superops+plan %.2f s"
+        % (rows, len(chans), len(blocks), kcount, plan_s))
     dm = P.DensityMatrix(rows, device="cuda:0")
     stream = torch.cuda.current_stream()
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in blocks]
@@ -706,7 +708,6 @@ def bench_density(args):
     st = dm.stats()
     sweeps = int(st["gate_sweeps"])
     tr, pur = dm.trace(), dm.purity()
-    dm.close()
     sweep_bytes = 16.0 * (1 << (2 * rows))
     per_class = {}
     for s in range(args.steps):
@@ -720,24 +721,52 @@ def bench_density(args):
                       "total_ms_per_step": float(np.sum(ts)) * 1e3 / args.steps,
                       "GBps": sweep_bytes / avg / 1e9, "frac": sweep_bytes / avg / 1e9 / HBM_PEAK_GBS}
     dom = max(kernels, key=lambda c: kernels[c]["total_ms_per_step"])
+    # the 6-target superoperator sweeps are FP32-MFMA work: 6 * 2^6 flops per amplitude (Gauss form)
+    mfma = None
+    if "k_tile_mfma<K=6> fp32" in kernels:
+        k6 = kernels["k_tile_mfma<K=6> fp32"]
+        tf = 6.0 * 64 * (1 << (2 * rows)) / (k6["avg_ms"] * 1e-3) / 1e12
+        mfma = {"kernel": "k_tile_mfma<K=6> fp32", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s",
+                "frac": tf / 157.3}
+
+    def plan_time(p, reps=3):
+        dm.reset()
+        p.run(dm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            dm.reset()
+            p.run(dm)
+            dm.sample(0x5EED, args.shots)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / reps
+
+    others = {}
+    for name, p in (("greedy_k6", P.Plan.greedy(2 * rows, gates, 6)), ("paper_pipeline", P.Plan.paper(2 * rows, gates))):
+        t = plan_time(p)
+        others[name] = {"blocks": len(p), "ms_per_step": t * 1e3, "learned_speedup": t / (el / args.steps)}
+    dm.close()
 
     out = {
-        "metric": "fused superoperator sweeps/s on a 15-qubit density matrix (vec(rho) 2^30 c64)",
-        "value": sweeps * args.steps / el, "unit": "superoperator-sweeps/s", "n_gpus": 1, "steps": args.steps,
+        "metric": "density-matrix channels/s: 15-qubit noisy brickwork, vec(rho) 2^30 c64",
+        "value": len(chans) * args.steps / el, "unit": "channels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "density matrix N=%d: noisy brickwork depth %d (Haar SU(2), CZ, 2-qubit depolarizing "
-                               "p=1e-3 after each CZ, seed %d), superoperators fused greedily to k<=%d vector "
-                               "qubits, %d shots" % (rows, depth, args.seed, kmax, args.shots),
+                               "p=1e-3 after each CZ, seed %d), superoperators fused by the learned planner, %d shots"
+                               % (rows, depth, args.seed, args.shots),
                    "channels": len(chans), "fused_blocks": len(blocks), "sweeps_per_step": sweeps,
-                   "blocks_by_k": kcount, "plan_and_superop_s": plan_s},
-        "channels_per_s": len(chans) * args.steps / el,
+                   "blocks_by_k": kcount, "superops_and_plan_s": plan_s},
+        "superoperator_sweeps_per_s": sweeps * args.steps / el,
         "final_trace": tr, "final_purity": pur,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": None,
-                     "launches": kernels[dom]["launches"], "avg_ms": kernels[dom]["avg_ms"],
-                     "bytes_per_launch": sweep_bytes},
-        "kernels": kernels, "cpu_baseline": None,
+        "roofline": (dict(mfma, bound="mfma", traffic=None, launches=kernels[dom]["launches"],
+                          avg_ms=kernels[dom]["avg_ms"], flops_per_launch=6.0 * 64 * (1 << (2 * rows)))
+                     if mfma is not None and dom == mfma["kernel"] else
+                     {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GBps"], "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": None,
+                      "launches": kernels[dom]["launches"], "avg_ms": kernels[dom]["avg_ms"],
+                      "bytes_per_launch": sweep_bytes}),
+        "kernels": kernels, "other_plans": others, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -99,7 +99,7 @@ def test_initial_state_and_reset(P):
     dm.close()
 
 
-@pytest.mark.parametrize("planner", ["greedy", "dp", "paper"])
+@pytest.mark.parametrize("planner", ["greedy", "dp", "paper", "learned"])
 def test_fused_superoperator_plans(P, planner):
     n = 5
     chans = Nz.noisy_brickwork(n, 3, 0.05, seed=7)
@@ -108,6 +108,9 @@ def test_fused_superoperator_plans(P, planner):
         plan = P.Plan.greedy(2 * n, gates, 6)
     elif planner == "dp":
         plan = P.Plan.dp(2 * n, gates, 6, 8, 64, reorder=True)
+    elif planner == "learned":
+        from paper_2608_16940_amd import costmodel as C
+        plan = P.Plan.learned(2 * n, gates, C.load()[0])
     else:
         plan = P.Plan.paper(2 * n, gates)
     assert len(plan) < len(gates)
