@@ -316,25 +316,54 @@ __device__ __forceinline__ uint64_t q_at(const float2 *psi, const double *probs,
 }
 
 // Exact total of each 2^10-entry block; workgroups stride over blocks (the
-// grid is capped below the 2^32 work-item limit of one dispatch).
+// grid is capped below the 2^32 work-item limit of one dispatch).  Thread t
+// takes entries 4t..4t+3 of the block with two 16-byte loads, the wave sums
+// by shuffles and four wave totals meet in LDS.  Integer sums do not depend
+// on the order, so the totals equal any other summation of the same q_x.
+// vec = 0 (a caller's probability array not 16-byte aligned) reads entry by entry.
+static_assert((1 << kCdfBlockBits) == 4 * kThreads, "one block = four entries per thread");
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const unsigned lo = __shfl_xor(unsigned(v), m), hi = __shfl_xor(unsigned(v >> 32), m);
+    v += (uint64_t(hi) << 32) | lo;
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(kThreads) void k_block_totals(const float2 *__restrict__ psi,
                                                            const double *__restrict__ probs, int64_t dim, int64_t nb,
-                                                           uint64_t *__restrict__ blocksum) {
-  __shared__ uint64_t red[kThreads];
+                                                           int vec, uint64_t *__restrict__ blocksum) {
+  __shared__ uint64_t red[kThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
-    const int64_t b0 = blk << kCdfBlockBits;
+    const int64_t x0 = (blk << kCdfBlockBits) + 4 * int64_t(threadIdx.x);
     uint64_t s = 0;
-    for (int i = threadIdx.x; i < (1 << kCdfBlockBits); i += kThreads) {
-      const int64_t x = b0 + i;
-      if (x < dim) s += q_at(psi, probs, x);
+    if (vec && x0 + 3 < dim) {
+      if (psi) {
+        const float4 a = reinterpret_cast<const float4 *>(psi)[x0 / 2];
+        const float4 b = reinterpret_cast<const float4 *>(psi)[x0 / 2 + 1];
+        s = fixed_q(prob_of(make_float2(a.x, a.y))) + fixed_q(prob_of(make_float2(a.z, a.w))) +
+            fixed_q(prob_of(make_float2(b.x, b.y))) + fixed_q(prob_of(make_float2(b.z, b.w)));
+      } else {
+        const double2 a = reinterpret_cast<const double2 *>(probs)[x0 / 2];
+        const double2 b = reinterpret_cast<const double2 *>(probs)[x0 / 2 + 1];
+        s = fixed_q(a.x) + fixed_q(a.y) + fixed_q(b.x) + fixed_q(b.y);
+      }
+    } else {
+      for (int j = 0; j < 4; ++j)
+        if (x0 + j < dim) s += q_at(psi, probs, x0 + j);
     }
-    red[threadIdx.x] = s;
+    s = wave_sum_u64(s);
+    if (lane == 0) red[wave] = s;
     __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+      blocksum[blk] = t;
     }
-    if (threadIdx.x == 0) blocksum[blk] = red[0];
     __syncthreads();
   }
 }
@@ -610,7 +639,9 @@ hipError_t launch_cdf_build(const float2 *psi, const double *probs, int n, const
   const int64_t dim = int64_t(1) << n;
   const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
   const int64_t gb = nb < (int64_t(1) << 20) ? nb : (int64_t(1) << 20);
-  hipLaunchKernelGGL(k_block_totals, dim3(unsigned(gb)), dim3(kThreads), 0, st, psi, probs, dim, nb, ws.blocksum);
+  const int vec = (psi || (reinterpret_cast<uintptr_t>(probs) & 15) == 0) ? 1 : 0;
+  hipLaunchKernelGGL(k_block_totals, dim3(unsigned(gb)), dim3(kThreads), 0, st, psi, probs, dim, nb, vec,
+                     ws.blocksum);
   const int64_t nc = (nb + 1023) / 1024;
   hipLaunchKernelGGL(k_scan_chunks, dim3(unsigned(nc)), dim3(kThreads), 0, st, ws.blocksum, nb, ws.chunksum);
   if (nc > 1) {

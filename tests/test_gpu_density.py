@@ -268,3 +268,31 @@ def test_full_size_entangling_channels_invariants(P):
     diag = rho[r, r].cpu().numpy()
     assert np.abs(diag.imag).max() <= 1e-6 and diag.real.min() >= -1e-6
     dm.close()
+
+
+def test_bound_superoperator_plan_and_graph_replays(P):
+    """A plan over superoperators bound to a density handle: eager run, bound run and HIP-graph
+    replays (with eager work between them) give bit-identical vec(rho), equal to the oracle."""
+    from paper_2608_16940_amd import costmodel as C
+    n = 6
+    rng = np.random.default_rng(77)
+    chans = Nz.noisy_brickwork(n, 3, 0.02, seed=11) + random_channels(n, 12, rng)
+    plan = P.Plan.learned(2 * n, P.superop_gates(n, chans), C.load()[0])
+    ref_dm = P.DensityMatrix(n)
+    plan.run(ref_dm)
+    ref = ref_dm.physical_state()
+    dm = P.DensityMatrix(n)
+    bound = plan.bind(dm)
+    bound.run()
+    np.testing.assert_array_equal(dm.physical_state(), ref)
+    for rep in range(3):
+        dm.reset()
+        bound.run_graph()
+        np.testing.assert_array_equal(dm.physical_state(), ref)
+        assert abs(dm.trace() - 1.0) <= TOL  # eager work between replays
+        dm.sample(rep, 50)
+    assert list(dm.layout()) == list(ref_dm.layout())
+    compare(dm, D.run(n, chans), "bound learned plan, %d blocks" % len(plan))
+    bound.close()
+    dm.close()
+    ref_dm.close()

@@ -284,11 +284,17 @@ def test_sampler_bit_exact_fixed_probabilities(P, n):
     p[rng.random(1 << n) < 0.3] = 0.0
     p /= p.sum()
     pd = torch.from_numpy(p).cuda()
+    # the same values 8 bytes into an allocation: the block totals read entry by entry
+    shifted = torch.zeros((1 << n) + 1, dtype=torch.float64, device=pd.device)
+    shifted[1:] = pd
+    pu = shifted[1:]
+    assert pu.data_ptr() % 16 == 8
     for seed in (0, 1, 0xDEADBEEFCAFE):
         got = P.sample_probs(pd, seed, 20_000)
         ref = oracle.sample(p, seed, 20_000)
         np.testing.assert_array_equal(got, ref)
         assert np.all(p[got.astype(np.int64)] > 0)
+        np.testing.assert_array_equal(P.sample_probs(pu, seed, 20_000), ref)
 
 
 def test_sampler_delta_and_state_decode(P):
