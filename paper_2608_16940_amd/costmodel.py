@@ -236,9 +236,12 @@ FIT_N = [24, 25, 26, 27, 28, 29, 30, 31, 32, 33]
 FIT_SAMPLES = [250, 250, 250, 300, 300, 250, 220, 160, 100, 60]
 
 
+FIT_REPS = 5  # timed sweeps per row (the median is the row's time)
+
+
 def fit(seed: int = 0, steps: int = 4000, log=print):
     """Collect sweep timings at N=24..33, hold out every fifth row, train, save."""
-    X, y, rows = collect(FIT_N, FIT_SAMPLES, seed=seed, log=log)
+    X, y, rows = collect(FIT_N, FIT_SAMPLES, seed=seed, reps=FIT_REPS, log=log)
     test = np.arange(len(y)) % 5 == 0
     t0 = time.perf_counter()
     params, hist = train(X[~test], y[~test], steps=steps, seed=seed, log_every=500)
@@ -247,6 +250,7 @@ def fit(seed: int = 0, steps: int = 4000, log=print):
     rmse_tr = float(np.sqrt(np.mean((pred[~test] - y[~test]) ** 2)))
     rmse_te = float(np.sqrt(np.mean((pred[test] - y[test]) ** 2)))
     meta = {"holdout": "every fifth row", "n_values": FIT_N, "samples": FIT_SAMPLES, "rows": int(len(y)),
+            "reps_per_row": FIT_REPS, "timed_sweeps": int(len(y)) * FIT_REPS,
             "train_steps": steps, "train_seconds": tt, "rmse_log_ms_train": rmse_tr, "rmse_log_ms_test": rmse_te,
             "loss_history": hist}
     save(params, meta=meta)
