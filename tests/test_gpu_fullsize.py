@@ -175,3 +175,46 @@ def test_probs_large_state_exact(P):
     assert torch.equal(p_log, want[phys])
     assert abs(float(p_phys.sum()) - 1) < 1e-5
     sv.close()
+
+
+def test_maximum_state_n35_closed_form(P):
+    """N=35, the largest state the interface accepts (256 GiB): a k=5 MFMA sweep on the top five
+    qubits, a shuffle sweep on qubit 0 and a diagonal CZ give a state whose 64 nonzero amplitudes
+    have a closed form; the FP64 norm and the sampler's support are checked too."""
+    import torch
+    n = 35
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    need = (8 << n) + (1 << 30)
+    if free < need:
+        pytest.skip("N=35 needs %.0f GiB of free device memory, %.0f GiB free" % (need / 2**30, free / 2**30))
+    say("n=35: %.0f GiB free" % (free / 2**30))
+    rng = np.random.default_rng(35)
+    top = (30, 31, 32, 33, 34)
+    G = W.random_dense(n, 5, rng, top).matrix
+    H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2)
+    sv = P.StateVector(n)
+    sv.apply(G, list(top))    # MFMA tile sweep, targets on the five highest bits
+    sv.apply(H, [0])          # wave-shuffle sweep on bit 0
+    sv.apply(W.cz(), [0, 30])  # streaming diagonal sweep
+    st = sv.stats()["by_variant"]
+    assert st[P._native.VARIANT["mfma"]] == 1 and st[P._native.VARIANT["shuffle"]] == 1
+    assert st[P._native.VARIANT["diag"]] == 1
+    xs, want = [], []
+    for r in range(32):
+        for b0 in range(2):
+            x = b0 | (r << 30)
+            sign = -1.0 if (b0 and (r & 1)) else 1.0
+            xs.append(x)
+            want.append(sign * G[r, 0] / math.sqrt(2))
+    got = gather(sv, np.array(xs, dtype=np.int64))
+    err = np.abs(got - np.array(want)).max()
+    nrm = sv.norm()
+    say("n=35 max|damp| %.2e on the 64 nonzero amplitudes, norm - 1 = %.2e" % (err, nrm - 1))
+    assert err < 1e-6 and abs(nrm - 1) < 1e-5
+    s = sv.sample(35, 2000)
+    support = np.uint64(1 | (31 << 30))
+    assert np.all((s & ~support) == 0)
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
