@@ -272,7 +272,11 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
 
     if constexpr (ALG == ALG_GAUSS_F32) {
       // step kk uses amplitude (AH h + kk) of this lane's group
-      constexpr int UNR = 8;
+      // unroll depth of the product loop, measured at N=30 on MI355X: k = 5
+      // rolled (5-7% faster than 8 steps at every target pattern), k = 6 and 7
+      // with the operand in LDS fully unrolled (9% and 15% faster); the
+      // cache-operand forms would spill fully unrolled and keep 8 steps
+      constexpr int UNR = (K == 5) ? 1 : (OPS == OP_LDS ? AH : 8);
 #pragma unroll UNR
       for (int kk = 0; kk < AH; ++kk) {
         const float2 x = lds[swz<K>(gbase | (h * AH + kk))];
