@@ -450,6 +450,27 @@ def bench_batch(args):
             worst_a = max(worst_a, max(abs(st[x] - v) for x, v in amps[i]))
         sample = {"circuits": len(zref), "max_abs_dz0": worst_z, "max_abs_amp_diff": worst_a,
                   "amplitudes_per_circuit": 16}
+    # baseline: the same circuits one launch per gate through sv_apply_fused (every 64th circuit, scaled)
+    import paper_2608_16940_amd as P
+    svs = {}
+    sample_idx = list(range(0, 4096, 64))
+    for i in sample_idx:  # allocate outside the timed region
+        n_i = circs[i][0]
+        if n_i not in svs:
+            svs[n_i] = P.StateVector(n_i)
+    sync()
+    t0 = time.perf_counter()
+    for i in sample_idx:
+        n_i, gates_i = circs[i]
+        sv = svs[n_i]
+        sv.reset()
+        for g in gates_i:
+            sv.apply(g.matrix, g.targets)
+    sync()
+    t_pg = time.perf_counter() - t0
+    per_gate_rate = len(sample_idx) / t_pg
+    for sv in svs.values():
+        sv.close()
     out = {
         "metric": "batched circuits/s (4096 circuits, one persistent launch)", "value": 4096 / t,
         "unit": "circuits/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -461,6 +482,8 @@ def bench_batch(args):
                      "unit": "GB/s", "frac": updates * 16 / t / 1e9 / lds_peak, "traffic": None,
                      "note": "16 B of LDS read + write per amplitude update (input gates, before fusion)"},
         "vs_oracle_golden_sample": sample,
+        "one_launch_per_gate": {"circuits_per_s": per_gate_rate, "sample": "every 64th circuit (%d), gate by gate "
+                                "through sv_apply_fused" % len(sample_idx), "batched_speedup": (4096 / t) / per_gate_rate},
     }
     print(json.dumps(out), flush=True)
 
