@@ -324,7 +324,10 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
       }
     } else {
       const shortx4 *oph = reinterpret_cast<const shortx4 *>(opsrc);
-      constexpr int UNR = (K <= 5) ? KQ : 4;
+      // fully unrolled up to k = 5, and at k = 6 with the operand in LDS (6.5%
+      // faster than 4 steps at N=30); k = 7 (operand through the caches) is
+      // fastest at 4 steps and the k = 6 cache form would spill unrolled
+      constexpr int UNR = (K <= 5 || (K == 6 && OPS == OP_LDS)) ? KQ : 4;
 #pragma unroll UNR
       for (int kk = 0; kk < KQ; ++kk) {
         // four reals = two amplitudes (AH h + 2 kk, +1)
