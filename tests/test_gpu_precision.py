@@ -1,4 +1,4 @@
-"""Wide fused sweeps (k=6, 7) in FP32 and BF16x3 at N=28 against the oracle.
+"""Wide fused sweeps (k=6, 7) in FP32 and BF16x3 at N=28 against the oracle, echo at N=28 and N=32.
 
 Brickwork depth 16 (seed 0) fused greedily with caps 6 and 7, and by the
 learned planner, run on the GPU in each MFMA precision; the result is compared
@@ -102,11 +102,16 @@ def test_wide_blocks_against_oracle_samples(P, which, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_echo_k7(P, prec):
-    gates = W.brickwork(N, 16, 0)
-    fwd = P.Plan.greedy(N, gates, 7)
-    inv = P.Plan.greedy(N, W.inverse(gates), 7)
-    sv = P.StateVector(N)
+@pytest.mark.parametrize("n", [N, 32])
+def test_echo_k7(P, prec, n):
+    """The fused circuit then its fused inverse returns |0...0>; at n=32 this is the
+    precision bench's own configuration (32 GiB, brickwork depth 16, greedy k<=7)."""
+    import torch
+    torch.cuda.empty_cache()
+    gates = W.brickwork(n, 16, 0)
+    fwd = P.Plan.greedy(n, gates, 7)
+    inv = P.Plan.greedy(n, W.inverse(gates), 7)
+    sv = P.StateVector(n)
     sv.set_precision(prec)
     fwd.run(sv)
     inv.run(sv)
@@ -114,7 +119,7 @@ def test_echo_k7(P, prec):
     a0 = abs(gather(sv, np.array([0], dtype=np.int64))[0]) ** 2
     # fidelity with |0...0> as the oracle defines it: overlap of the normalized states
     f0 = a0 / nrm
-    say("echo n28 k7 %s: fidelity %.9f  norm-1 %.3e" % (prec, f0, nrm - 1))
+    say("echo n%d k7 %s: fidelity %.9f  norm-1 %.3e" % (n, prec, f0, nrm - 1))
     assert f0 >= 1 - 1e-5
     assert abs(nrm - 1) <= REL[prec]
     sv.close()
