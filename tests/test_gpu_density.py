@@ -296,3 +296,36 @@ def test_bound_superoperator_plan_and_graph_replays(P):
     bound.close()
     dm.close()
     ref_dm.close()
+
+
+@pytest.mark.parametrize("p_noise", [0.0, 1e-3])
+def test_bench_configuration_n15(P, p_noise):
+    """The density bench's configuration (N=15, noisy brickwork depth 8, learned plan over
+    superoperators).  With p = 0 the result is |psi><psi| with psi from the state-vector oracle
+    (compared at 4096 sampled entries); with the bench's p = 1e-3: trace, Hermiticity, purity."""
+    import torch
+    from paper_2608_16940_amd import costmodel as C
+    n = 15
+    chans = Nz.noisy_brickwork(n, 8, p_noise, 0)
+    plan = P.Plan.learned(2 * n, P.superop_gates(n, chans), C.load()[0])
+    dm = P.DensityMatrix(n)
+    plan.run(dm)
+    rho = dm.matrix()
+    rng = np.random.default_rng(15)
+    d = 1 << n
+    r = rng.integers(0, d, 4096)
+    c = rng.integers(0, d, 4096)
+    got = rho[torch.as_tensor(r, device=rho.device), torch.as_tensor(c, device=rho.device)].cpu().numpy()
+    tr, pur = dm.trace(), dm.purity()
+    if p_noise == 0.0:
+        psi = oracle.run(n, W.brickwork(n, 8, 0))
+        want = psi[r] * psi[c].conj()
+        err = np.abs(got - want).max()
+        say("n=15 p=0 learned plan (%d blocks): max|drho| %.2e, trace %.8f, purity %.8f" % (len(plan), err, tr, pur))
+        assert err <= TOL and abs(pur - 1) <= TOL
+    else:
+        back = rho[torch.as_tensor(c, device=rho.device), torch.as_tensor(r, device=rho.device)].cpu().numpy()
+        say("n=15 p=1e-3 learned plan (%d blocks): trace %.8f, purity %.6f" % (len(plan), tr, pur))
+        assert np.abs(got - back.conj()).max() <= 1e-6 and 0 < pur < 1
+    assert abs(tr - 1) <= TOL
+    dm.close()
