@@ -85,6 +85,8 @@ def is_qubit_permutation(m):
 
 def kernel_class(b, n):
     """The lowering sv_apply_fused picks for a block (its automatic selector)."""
+    if b.get("swap"):
+        return "k_tile_permute (layout swap)"
     if is_qubit_permutation(b["matrix"]):
         return "layout"  # absorbed by the layout map: no kernel
     if b["diag"]:
@@ -97,6 +99,22 @@ def kernel_class(b, n):
     if k <= 4:
         return "k_dense_valu<%d>" % k
     return "k_dense_generic"
+
+
+def apply_block(sv, b):
+    """One plan block as sv_run_plan applies it: a fused matrix, or a layout swap."""
+    if b.get("swap"):
+        L = [int(x) for x in sv.layout()]
+        inv = {p: q for q, p in enumerate(L)}
+        for q, to in zip(b["targets"], b["dest"]):
+            frm = L[q]
+            if frm != to:
+                r = inv[to]
+                L[q], L[r] = to, frm
+                inv[to], inv[frm] = q, r
+        sv.permute_layout(L)
+    else:
+        sv.apply(b["matrix"], b["targets"])
 
 
 def cpu_baseline(n, gates, n_blocks, seconds):
@@ -198,10 +216,10 @@ def main():
             if timed_index is not None:
                 e0, e1 = ev[timed_index][j]
                 e0.record(stream)
-                sv.apply(b["matrix"], b["targets"])
+                apply_block(sv, b)
                 e1.record(stream)
             else:
-                sv.apply(b["matrix"], b["targets"])
+                apply_block(sv, b)
         return sv.sample(0x5EED, args.shots)
 
     for w in range(args.warmup):
@@ -261,7 +279,8 @@ def main():
         t_b = step_time(plan, 3, "bf16x3")
         kl = {}
         for b in lplan.blocks():
-            kl[str(b["k"])] = kl.get(str(b["k"]), 0) + 1
+            key = "swap" if b.get("swap") else str(b["k"])
+            kl[key] = kl.get(key, 0) + 1
         extra = {
             "learned_plan": {"blocks": len(lplan), "blocks_by_k": kl, "ms_per_step": t_l * 1e3,
                              "speedup_vs_greedy_step": (el / args.steps) / t_l},
@@ -365,8 +384,10 @@ def bench_learned(args):
         log("bench learned: %s %d blocks, execute %.3f s" % (name, len(fwd), ex))
         ks = {}
         for b in fwd.blocks():
-            ks[str(b["k"])] = ks.get(str(b["k"]), 0) + 1
+            key = "swap" if b.get("swap") else str(b["k"])
+            ks[key] = ks.get(key, 0) + 1
         res[name] = {"blocks": len(fwd), "diag_blocks": sum(1 for b in fwd.blocks() if b["diag"]),
+                     "layout_swaps": int(getattr(fwd, "swaps_inserted", 0)),
                      "blocks_by_k": ks, "plan_s": plan_s, "execute_s": ex, "end_to_end_s": plan_s + ex}
         if name == "paper":  # context only: no echo (another ~900 sweeps)
             continue
@@ -384,6 +405,8 @@ def bench_learned(args):
     def predicted(plan):
         tot = 0.0
         for b in plan.blocks():
+            if b.get("swap"):
+                continue
             f = C.features(n, list(b["targets"]), b["diag"])
             tot += float(np.exp(C.forward_host(params, f[None])[0] + (n - 30) * np.log(2.0)))
         return tot / 1e3
@@ -701,7 +724,8 @@ def bench_density(args):
     classes = [kernel_class(b, 2 * rows) for b in blocks]
     kcount = {}
     for b in blocks:
-        kcount[str(b["k"])] = kcount.get(str(b["k"]), 0) + 1
+        key = "swap" if b.get("swap") else str(b["k"])
+        kcount[key] = kcount.get(key, 0) + 1
     log("bench density: N=%d channels=%d learned blocks=%d by_k=%s superops+plan %.2f s"
         % (rows, len(chans), len(blocks), kcount, plan_s))
     dm = P.DensityMatrix(rows, device="cuda:0")
@@ -713,10 +737,10 @@ def bench_density(args):
         dm.reset()
         for j, b in enumerate(blocks):
             if i is None:
-                dm.apply(b["matrix"], b["targets"])
+                apply_block(dm, b)
             else:
                 ev[i][j][0].record(stream)
-                dm.apply(b["matrix"], b["targets"])
+                apply_block(dm, b)
                 ev[i][j][1].record(stream)
         return dm.sample(0x5EED, args.shots)
 

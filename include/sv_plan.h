@@ -86,13 +86,49 @@ int sv_cost_features(int n_qubits, int k, const int32_t *phys_targets, int diago
 /* Number of fused blocks. */
 int sv_plan_num_blocks(const sv_plan *p, int *out);
 
-/* Block i: width, ordered logical targets (host int32[8]), gate count, diagonal flag. */
+/* Block i: width k, ordered logical targets (host int32[k]: k <= 8 for a fused
+ * block, up to 14 for a layout-swap block; pass targets = null to read k
+ * first), gate count, diagonal flag. */
 int sv_plan_block_info(const sv_plan *p, int i, int *k, int32_t *targets, int *n_gates, int *diag);
 
-/* Block i's FP64 fused matrix (2 * 4^k doubles, complex128 row-major interleaved). */
+/* Block i's FP64 fused matrix (2 * 4^k doubles, complex128 row-major
+ * interleaved).  SV_ERR_ARG for a layout-swap block, which has none. */
 int sv_plan_block_matrix(const sv_plan *p, int i, double *out);
 
-/* Apply every block in order through sv_apply_fused. */
+/*
+ * Layout swaps chosen by the learned cost model (an addition to the paper:
+ * its placement policy, Corollary 1 and Eq. lazy-vol, decides where qubits
+ * go by next use; here the model decides whether moving them pays).  The
+ * pass walks the plan with the layout a run from the identity layout would
+ * have (blocks that only permute qubits update it, as in sv_apply_fused).
+ * Before each dense, non-permutation block it considers moving the block's
+ * targets onto every window of k consecutive physical bits (each target that
+ * is outside the window exchanged with the qubit on a free window bit) and
+ * predicts, with the model, the time the next `horizon` blocks gain at their
+ * new physical positions.  It inserts the best move as a layout-swap block
+ * when that gain exceeds the predicted cost of the permutation sweeps
+ * (ceil(exchanges / 5) in-place tile passes, each priced as a streaming
+ * sweep times SV_PLAN_SWAP_SWEEP_FACTOR) by more than the factor
+ * (1 + margin).  A swap block changes only where qubits are stored, never
+ * the logical state.  States under SV_PLAN_SWAP_MIN_QUBITS qubits get no
+ * swaps: the model was trained from 24 qubits up, and smaller states stay in
+ * the caches, where the placement of target bits matters little.
+ * mlp_params_host: the cost model as in sv_plan_dp.  *inserted (may be null):
+ * swap blocks added.  Errors: SV_ERR_ARG.
+ */
+#define SV_PLAN_SWAP_SWEEP_FACTOR 1.15
+#define SV_PLAN_SWAP_MIN_QUBITS 24
+int sv_plan_swaps(sv_plan *p, const float *mlp_params_host, int mlp_nin, int mlp_hid, int horizon, double margin,
+                  int *inserted);
+
+/* Block i a layout-swap block?  *is_swap = 1 and dest (host int32[k], may be
+ * null) holds the physical bit each of its logical targets goes to; else
+ * *is_swap = 0. */
+int sv_plan_block_swap(const sv_plan *p, int i, int *is_swap, int32_t *dest);
+
+/* Apply every block in order: fused blocks through sv_apply_fused, layout-
+ * swap blocks through sv_permute_layout (each listed logical qubit moved to
+ * its physical bit, the qubit found there taking its old place). */
 int sv_run_plan(sv_state *s, const sv_plan *p);
 
 int sv_plan_free(sv_plan *p);
@@ -119,7 +155,8 @@ int sv_plan_free(sv_plan *p);
  *   sv_bound_free       release the host object (and the graph)
  * The bound plan keeps pointers to the handle and to op_dev: free it before
  * either.  Errors: SV_ERR_ARG (relabel on, buffer too small or misaligned,
- * layout changed since binding), SV_ERR_UNSUPPORTED, SV_ERR_DEVICE.
+ * layout changed since binding), SV_ERR_UNSUPPORTED (a plan with layout-swap
+ * blocks: run it with sv_run_plan), SV_ERR_DEVICE.
  */
 typedef struct sv_bound sv_bound;
 int sv_bound_bytes(sv_state *s, const sv_plan *p, size_t *out);

@@ -232,10 +232,23 @@ class Plan:
         return cls.dp(n, gates, k_max=k_max, diag_max=diag_max, window=window, reorder=True, repeat=True)
 
     @classmethod
-    def learned(cls, n: int, gates, params, k_max: int = 7, window: int = 64) -> "Plan":
-        """The learned planner: the same pipeline on predicted sweep times, dense cap chosen by the model."""
-        return cls.dp(n, gates, k_max=k_max, diag_max=k_max, window=window, params=params, reorder=True,
+    def learned(cls, n: int, gates, params, k_max: int = 7, window: int = 64, swaps: bool = True,
+                horizon: int = 32, margin: float = 0.25) -> "Plan":
+        """The learned planner: the same pipeline on predicted sweep times, dense cap chosen by the model,
+        then (swaps=True) layout swaps where the model predicts they pay (sv_plan_swaps)."""
+        plan = cls.dp(n, gates, k_max=k_max, diag_max=k_max, window=window, params=params, reorder=True,
                       search_cap=True, repeat=True)
+        if swaps:
+            plan.swaps_inserted = plan.add_swaps(params, horizon, margin)
+        return plan
+
+    def add_swaps(self, params, horizon: int = 32, margin: float = 0.25, nin: int = 10, hid: int = 64) -> int:
+        """Insert layout-swap blocks where the cost model predicts a net gain; returns how many."""
+        params = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        out = ctypes.c_int()
+        check(lib().sv_plan_swaps(self._h, params.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(nin),
+                                  int(hid), int(horizon), float(margin), ctypes.byref(out)))
+        return out.value
 
     def __len__(self) -> int:
         v = ctypes.c_int()
@@ -243,12 +256,20 @@ class Plan:
         return v.value
 
     def block(self, i: int):
+        """A fused block {k, targets, n_gates, diag, matrix}, or a layout-swap block
+        {k, targets, swap: True, dest} (logical targets[j] moves to physical bit dest[j])."""
         k = ctypes.c_int()
         ng = ctypes.c_int()
         dg = ctypes.c_int()
-        t = np.zeros(8, dtype=np.int32)
+        t = np.zeros(64, dtype=np.int32)
         check(lib().sv_plan_block_info(self._h, int(i), ctypes.byref(k), t.ctypes.data_as(_native._i32p),
                                        ctypes.byref(ng), ctypes.byref(dg)))
+        sw = ctypes.c_int()
+        dest = np.zeros(64, dtype=np.int32)
+        check(lib().sv_plan_block_swap(self._h, int(i), ctypes.byref(sw), dest.ctypes.data_as(_native._i32p)))
+        if sw.value:
+            return {"k": k.value, "targets": tuple(int(x) for x in t[:k.value]), "swap": True,
+                    "dest": tuple(int(x) for x in dest[:k.value]), "n_gates": 0, "diag": False}
         m = np.empty((1 << k.value, 1 << k.value), dtype=np.complex128)
         check(lib().sv_plan_block_matrix(self._h, int(i), m.view(np.float64).ctypes.data_as(_native._dp)))
         return {"k": k.value, "targets": tuple(int(x) for x in t[:k.value]), "n_gates": ng.value,

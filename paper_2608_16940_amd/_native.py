@@ -116,6 +116,9 @@ SIGNATURES = [
                                    ctypes.c_float, ctypes.c_float, _vp]),
     ("sv_mlp_forward_host", ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_float), ctypes.c_int, _dp]),
+    ("sv_plan_swaps", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.POINTER(ctypes.c_int)]),
+    ("sv_plan_block_swap", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _i32p]),
     ("sv_plan_dp", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, _i32p, _dp, ctypes.POINTER(ctypes.c_int8),
                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int, ctypes.c_int,

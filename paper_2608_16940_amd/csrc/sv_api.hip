@@ -50,6 +50,37 @@ size_t workspace_layout(int n, char *base, Workspace *ws) {
 
 }  // namespace sv
 
+namespace sv {
+
+// True when G maps each basis state |c> to |pi(c)>, pi moving bit j of c to
+// bit perm[j] (a permutation of the block's qubits), with exact 0/1 entries.
+bool qubit_permutation(const double *G, int k, int *perm) {
+  const int D = 1 << k;
+  for (int i = 0; i < D * D; ++i)
+    if (G[2 * i + 1] != 0.0 || (G[2 * i] != 0.0 && G[2 * i] != 1.0)) return false;
+  int used = 0;
+  for (int j = 0; j < k; ++j) {
+    int row = -1;
+    for (int r = 0; r < D; ++r)
+      if (G[2 * (r * D + (1 << j))] == 1.0) {
+        if (row >= 0) return false;
+        row = r;
+      }
+    if (row <= 0 || (row & (row - 1)) || (used & row)) return false;
+    used |= row;
+    perm[j] = __builtin_ctz(unsigned(row));
+  }
+  for (int c = 0; c < D; ++c) {
+    int r = 0;
+    for (int j = 0; j < k; ++j) r |= ((c >> j) & 1) << perm[j];
+    for (int rr = 0; rr < D; ++rr)
+      if (G[2 * (rr * D + c)] != (rr == r ? 1.0 : 0.0)) return false;
+  }
+  return true;
+}
+
+}  // namespace sv
+
 using namespace sv;
 
 
@@ -303,33 +334,6 @@ int launch_lowered(sv_state *s, const Lowered &L, const void *op_dev) {
   s->stats.launches += 1;
   if (L.variant >= 0 && L.variant < 6) s->stats.by_variant[L.variant] += 1;
   return SV_OK;
-}
-
-// True when G maps each basis state |c> to |pi(c)>, pi moving bit j of c to
-// bit perm[j] (a permutation of the block's qubits), with exact 0/1 entries.
-bool qubit_permutation(const double *G, int k, int *perm) {
-  const int D = 1 << k;
-  for (int i = 0; i < D * D; ++i)
-    if (G[2 * i + 1] != 0.0 || (G[2 * i] != 0.0 && G[2 * i] != 1.0)) return false;
-  int used = 0;
-  for (int j = 0; j < k; ++j) {
-    int row = -1;
-    for (int r = 0; r < D; ++r)
-      if (G[2 * (r * D + (1 << j))] == 1.0) {
-        if (row >= 0) return false;
-        row = r;
-      }
-    if (row <= 0 || (row & (row - 1)) || (used & row)) return false;
-    used |= row;
-    perm[j] = __builtin_ctz(unsigned(row));
-  }
-  for (int c = 0; c < D; ++c) {
-    int r = 0;
-    for (int j = 0; j < k; ++j) r |= ((c >> j) & 1) << perm[j];
-    for (int rr = 0; rr < D; ++rr)
-      if (G[2 * (rr * D + c)] != (rr == r ? 1.0 : 0.0)) return false;
-  }
-  return true;
 }
 
 int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
@@ -838,6 +842,13 @@ int lower_plan(sv_state *s, const sv_plan *p, std::vector<Lowered> *ops, std::ve
   int32_t L[64];  // the layout as the run will see it block by block
   std::memcpy(L, s->L, sizeof(L));
   for (int i = 0; i < nb; ++i) {
+    int sw = 0;
+    rc = sv_plan_block_swap(p, i, &sw, nullptr);
+    if (rc) return rc;
+    if (sw) {
+      set_error("a plan with layout-swap blocks runs through sv_run_plan, not as a bound plan");
+      return SV_ERR_UNSUPPORTED;
+    }
     int k = 0, ng = 0, dg = 0;
     int32_t t[8];
     rc = sv_plan_block_info(p, i, &k, t, &ng, &dg);

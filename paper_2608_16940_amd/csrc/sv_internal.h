@@ -109,6 +109,11 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out);
 bool make_gate_tile(int n, int K, const int32_t *A, uint64_t extra, TilePlan *tp);
 int mfma_tile_M(int K);
 
+// True when the 2^k x 2^k complex128 matrix G (row-major interleaved) maps
+// every basis state |c> to |pi(c)>, pi moving bit j of c to bit perm[j]: a
+// permutation of the block's qubits, which the layout map absorbs.
+bool qubit_permutation(const double *G, int k, int *perm);
+
 // opsrc: SV_MFMA_OPERAND_* (where k <= 5 waves keep the embedded operand).
 hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi, const void *operand_dev,
                             hipStream_t st);

@@ -13,6 +13,7 @@
 
 namespace sv {
 void set_error(const std::string &msg);
+bool qubit_permutation(const double *G, int k, int *perm);
 }
 
 struct SvBlock {
@@ -21,6 +22,8 @@ struct SvBlock {
   bool diag = true;
   std::vector<int32_t> tuple;    // ordered logical targets (ascending)
   std::vector<double> matrix;    // complex128 interleaved, 2^k x 2^k
+  bool swap = false;             // a layout-swap block: no matrix, tuple[j] goes to physical bit dest[j]
+  std::vector<int32_t> dest;
 };
 
 struct sv_plan {
@@ -208,7 +211,23 @@ int sv_plan_block_matrix(const sv_plan *p, int i, double *out) {
     return SV_ERR_ARG;
   }
   const SvBlock &b = p->blocks[size_t(i)];
+  if (b.swap) {
+    sv::set_error("a layout-swap block has no matrix");
+    return SV_ERR_ARG;
+  }
   std::memcpy(out, b.matrix.data(), b.matrix.size() * sizeof(double));
+  return SV_OK;
+}
+
+int sv_plan_block_swap(const sv_plan *p, int i, int *is_swap, int32_t *dest) {
+  if (!p || !is_swap || i < 0 || i >= int(p->blocks.size())) {
+    sv::set_error("bad block index");
+    return SV_ERR_ARG;
+  }
+  const SvBlock &b = p->blocks[size_t(i)];
+  *is_swap = b.swap ? 1 : 0;
+  if (b.swap && dest)
+    for (int j = 0; j < b.k; ++j) dest[j] = b.dest[size_t(j)];
   return SV_OK;
 }
 
@@ -224,11 +243,32 @@ int sv_run_plan(sv_state *s, const sv_plan *p) {
   std::vector<std::vector<int64_t>> hints(nb);
   for (size_t i = nb; i-- > 0;) {
     hints[i] = next;
-    for (int32_t q : p->blocks[i].tuple) next[size_t(q)] = int64_t(i);
+    if (!p->blocks[i].swap)
+      for (int32_t q : p->blocks[i].tuple) next[size_t(q)] = int64_t(i);
   }
   for (size_t i = 0; i < nb; ++i) {
     const SvBlock &b = p->blocks[i];
-    int rc = sv_hint_next_use(s, hints[i].data());
+    int rc;
+    if (b.swap) {
+      // each listed qubit to its physical bit, the occupant to its old place
+      std::vector<int32_t> L(static_cast<size_t>(p->n)), Linv(static_cast<size_t>(p->n));
+      rc = sv_get_layout(s, L.data());
+      if (rc) return rc;
+      for (int q = 0; q < p->n; ++q) Linv[size_t(L[size_t(q)])] = q;
+      for (int j = 0; j < b.k; ++j) {
+        const int32_t q = b.tuple[size_t(j)], to = b.dest[size_t(j)], from = L[size_t(q)];
+        if (from == to) continue;
+        const int32_t r = Linv[size_t(to)];
+        L[size_t(q)] = to;
+        L[size_t(r)] = from;
+        Linv[size_t(to)] = q;
+        Linv[size_t(from)] = r;
+      }
+      rc = sv_permute_layout(s, L.data());
+      if (rc) return rc;
+      continue;
+    }
+    rc = sv_hint_next_use(s, hints[i].data());
     if (rc) return rc;
     rc = sv_apply_fused(s, b.matrix.data(), b.tuple.data(), b.k);
     if (rc) return rc;
@@ -556,5 +596,127 @@ extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *t
     return SV_OK;
   }
   *out = build_plan(n, gates, dp_rounds(n, gates, k_max, diag_max, window, flags, gamma));
+  return SV_OK;
+}
+
+// ------------------------------------------------------------------ layout swaps chosen by the cost model
+namespace {
+
+// Apply a block that only permutes qubits to a layout, as sv_apply_fused
+// does: L'(t[perm[j]]) = L(t[j]).
+bool absorb_permutation(const SvBlock &b, std::vector<int32_t> *L) {
+  if (b.swap || b.k > SV_MAX_K) return false;
+  int perm[SV_MAX_K];
+  if (!sv::qubit_permutation(b.matrix.data(), b.k, perm)) return false;
+  int32_t old[SV_MAX_K];
+  for (int j = 0; j < b.k; ++j) old[j] = (*L)[size_t(b.tuple[size_t(j)])];
+  for (int j = 0; j < b.k; ++j) (*L)[size_t(b.tuple[size_t(perm[j])])] = old[j];
+  return true;
+}
+
+// The layout after moving the logical qubits `tuple` onto physical bits
+// s0 .. s0+k-1: targets already there stay; each other target, in order of
+// its current position, exchanges places with the qubit on the lowest free
+// window bit.  *moves = the exchanges made.
+std::vector<int32_t> move_onto(const std::vector<int32_t> &L, const std::vector<int32_t> &tuple, int s0,
+                               int *moves) {
+  const int n = int(L.size()), k = int(tuple.size());
+  std::vector<int32_t> L2(L), Linv(static_cast<size_t>(n));
+  for (int q = 0; q < n; ++q) Linv[size_t(L2[size_t(q)])] = q;
+  std::vector<char> is_target(static_cast<size_t>(n), 0);
+  for (int32_t q : tuple) is_target[size_t(q)] = 1;
+  std::vector<int32_t> movers, free_bits;
+  for (int32_t q : tuple)
+    if (L2[size_t(q)] < s0 || L2[size_t(q)] >= s0 + k) movers.push_back(q);
+  std::sort(movers.begin(), movers.end(), [&](int32_t a, int32_t b) { return L2[size_t(a)] < L2[size_t(b)]; });
+  for (int p = s0; p < s0 + k; ++p)
+    if (!is_target[size_t(Linv[size_t(p)])]) free_bits.push_back(p);
+  for (size_t j = 0; j < movers.size(); ++j) {
+    const int32_t q = movers[j], to = free_bits[j], from = L2[size_t(q)], r = Linv[size_t(to)];
+    L2[size_t(q)] = to;
+    L2[size_t(r)] = from;
+    Linv[size_t(to)] = q;
+    Linv[size_t(from)] = r;
+  }
+  *moves = int(movers.size());
+  return L2;
+}
+
+}  // namespace
+
+extern "C" int sv_plan_swaps(sv_plan *p, const float *mlp_params, int mlp_nin, int mlp_hid, int horizon,
+                             double margin, int *inserted) {
+  if (!p || !mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1 || horizon < 1 || margin < 0) {
+    sv::set_error("bad swap-pass argument");
+    return SV_ERR_ARG;
+  }
+  if (inserted) *inserted = 0;
+  const int n = p->n;
+  if (n < SV_PLAN_SWAP_MIN_QUBITS) return SV_OK;
+  Scorer gamma{SV_SCORE_LEARNED, n, mlp_params, mlp_nin, mlp_hid, {}};
+  auto cost = [&](const SvBlock &b, const std::vector<int32_t> &L) {
+    std::vector<int32_t> ph;
+    for (int32_t q : b.tuple) ph.push_back(L[size_t(q)]);
+    std::sort(ph.begin(), ph.end());
+    return gamma(ph, b.diag);
+  };
+  const double stream = gamma(std::vector<int32_t>{0}, true);  // one streaming sweep
+  std::vector<int32_t> L(static_cast<size_t>(n));
+  for (int q = 0; q < n; ++q) L[size_t(q)] = q;
+  std::vector<SvBlock> out;
+  const size_t nb = p->blocks.size();
+  int added = 0;
+  for (size_t i = 0; i < nb; ++i) {
+    const SvBlock &b = p->blocks[i];
+    std::vector<int32_t> Lperm(L);
+    const bool permutes = absorb_permutation(b, &Lperm);
+    if (!b.swap && !b.diag && !permutes && b.k <= 7) {
+      double best = 0.0;
+      std::vector<int32_t> bestL;
+      for (int s0 = 0; s0 + b.k <= n; ++s0) {
+        int moves = 0;
+        std::vector<int32_t> L2 = move_onto(L, b.tuple, s0, &moves);
+        if (moves == 0) continue;
+        // the next `horizon` blocks at their positions under both layouts
+        std::vector<int32_t> La(L), Lb(L2);
+        double gain = 0.0;
+        for (size_t j = i; j < nb && j < i + size_t(horizon); ++j) {
+          const SvBlock &c = p->blocks[j];
+          if (c.swap) break;
+          if (absorb_permutation(c, &La)) {
+            absorb_permutation(c, &Lb);
+            continue;
+          }
+          if (!c.diag) gain += cost(c, La) - cost(c, Lb);
+        }
+        const double price = double((moves + 4) / 5) * stream * SV_PLAN_SWAP_SWEEP_FACTOR;
+        if (gain > price * (1.0 + margin) && gain - price > best) {
+          best = gain - price;
+          bestL = std::move(L2);
+        }
+      }
+      if (!bestL.empty()) {
+        SvBlock sw;
+        sw.swap = true;
+        sw.ngates = 0;
+        sw.diag = false;
+        for (int q = 0; q < n; ++q)
+          if (bestL[size_t(q)] != L[size_t(q)]) {
+            sw.tuple.push_back(q);
+            sw.dest.push_back(bestL[size_t(q)]);
+          }
+        sw.k = int(sw.tuple.size());
+        out.push_back(std::move(sw));
+        L = bestL;
+        Lperm = L;
+        absorb_permutation(b, &Lperm);
+        ++added;
+      }
+    }
+    out.push_back(b);
+    L = Lperm;
+  }
+  p->blocks = std::move(out);
+  if (inserted) *inserted = added;
   return SV_OK;
 }

@@ -143,6 +143,8 @@ def test_reordered_plans_keep_each_qubits_gate_order(P, C):
                  P.Plan.dp(n, gates, 3, 3, 8, reorder=True)]:
         psi = oracle.zero_state(n)
         for b in plan.blocks():
+            if b.get("swap"):
+                continue  # a layout swap moves storage, not the logical state
             oracle.apply_gate(psi, b["matrix"], b["targets"])
         m = oracle.metrics(ref, psi)
         assert m["infidelity"] < 1e-12 and m["max_abs"] < 1e-12
@@ -158,7 +160,7 @@ def test_learned_planner_search_prefers_cheaper_plan(P, C):
 
     def predicted(plan):
         return sum(float(np.exp(C.forward_host(params, C.features(n, list(b["targets"]), b["diag"])[None])[0]))
-                   for b in plan.blocks())
+                   for b in plan.blocks() if not b.get("swap"))
     best = predicted(P.Plan.learned(n, gates, params))
     for cap in (4, 5, 6, 7):
         assert best <= predicted(P.Plan.dp(n, gates, cap, cap, 64, params=params, reorder=True)) + 1e-9
@@ -177,8 +179,95 @@ def test_repeated_rounds_exact_and_never_worse(P, C):
     for plan in (again, P.Plan.paper(n, gates), P.Plan.learned(n, gates, C.init_params(6))):
         psi = oracle.zero_state(n)
         for b in plan.blocks():
+            if b.get("swap"):
+                continue
             assert b["k"] <= 7
             oracle.apply_gate(psi, b["matrix"], b["targets"])
         m = oracle.metrics(ref, psi)
         assert m["infidelity"] < 1e-12 and m["max_abs"] < 1e-12
         assert sum(b["n_gates"] for b in plan.blocks()) == len(gates)
+
+
+# ---------------------------------------------------------------- layout swaps chosen by the cost model
+def alternating_case(n=30, reps=20, seed=0):
+    """Dense 4-qubit gates alternating between qubits 20..23 (slow target bits on MI355X) and 0..3."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(reps):
+        gates.append(W.random_dense(n, 4, rng, (20, 21, 22, 23)))
+        gates.append(W.random_dense(n, 4, rng, (0, 1, 2, 3)))
+    return gates
+
+
+def predicted_with_layout(C, params, n, plan, factor=1.15):
+    """Model time of a plan run from the identity layout, swaps priced as the pass prices them."""
+    L = list(range(n))
+    stream = float(np.exp(C.forward_host(params, C.features(n, [0], True)[None])[0]))
+    tot = 0.0
+    for b in plan.blocks():
+        if b.get("swap"):
+            for q, d in zip(b["targets"], b["dest"]):
+                L[q] = d
+            moves = len(b["targets"]) // 2  # each exchange lists two qubits
+            tot += stream * factor * ((moves + 4) // 5)
+            continue
+        ph = [L[q] for q in b["targets"]]
+        tot += float(np.exp(C.forward_host(params, C.features(n, ph, b["diag"])[None])[0]))
+    return tot
+
+
+def test_swap_pass_moves_slow_targets_when_the_model_predicts_a_gain(P, C):
+    if not os.path.exists(C.WEIGHTS):
+        pytest.skip("no committed cost model")
+    params, _ = C.load()
+    n = 30
+    gates = alternating_case(n)
+    base = P.Plan.greedy(n, gates, 4)
+    plan = P.Plan.greedy(n, gates, 4)
+    assert plan.add_swaps(params) == 1
+    blocks = plan.blocks()
+    assert len(blocks) == len(base) + 1 and blocks[0].get("swap")
+    sw = blocks[0]
+    moved = dict(zip(sw["targets"], sw["dest"]))
+    # qubits 20..23 leave their bits for a window of four consecutive bits, the occupants take their place
+    new = sorted(moved[q] for q in (20, 21, 22, 23))
+    assert new == list(range(new[0], new[0] + 4)) and set(new).isdisjoint({0, 1, 2, 3})
+    assert sorted(sw["dest"]) == sorted(sw["targets"])
+    assert predicted_with_layout(C, params, n, plan) < predicted_with_layout(C, params, n, base)
+    # the fused blocks are untouched, so the logical circuit is the same
+    for a, b in zip([b for b in blocks if not b.get("swap")], base.blocks()):
+        assert a["targets"] == b["targets"] and np.array_equal(a["matrix"], b["matrix"])
+
+
+def test_swap_pass_inserts_nothing_where_no_gain_is_predicted(P, C):
+    if not os.path.exists(C.WEIGHTS):
+        pytest.skip("no committed cost model")
+    params, _ = C.load()
+    plan = P.Plan.learned(30, W.brickwork(30, 6, 0) + W.qft(30), params)
+    assert plan.swaps_inserted == 0
+    small = P.Plan.greedy(10, W.brickwork(10, 4, 0), 4)
+    assert small.add_swaps(params) == 0  # states under 24 qubits get none
+    with pytest.raises(P.SvError):
+        small.add_swaps(params, margin=-1.0)
+
+
+def test_swap_blocks_keep_the_logical_state(P, C):
+    """Oracle: the fused blocks of a plan with swaps (N=24, the smallest size the pass acts on),
+    applied in order, equal the unfused circuit."""
+    if not os.path.exists(C.WEIGHTS):
+        pytest.skip("no committed cost model")
+    params, _ = C.load()
+    n = 24
+    rng = np.random.default_rng(3)
+    gates = []
+    for _ in range(6):
+        gates.append(W.random_dense(n, 4, rng, (18, 19, 20, 21)))
+        gates.append(W.random_dense(n, 3, rng, (0, 1, 2)))
+    plan = P.Plan.greedy(n, gates, 4)
+    print("swaps at N=24:", plan.add_swaps(params))
+    psi = oracle.zero_state(n)
+    for b in plan.blocks():
+        if not b.get("swap"):
+            oracle.apply_gate(psi, b["matrix"], b["targets"])
+    m = oracle.metrics(oracle.run(n, gates), psi)
+    assert m["infidelity"] < 1e-12 and m["max_abs"] < 1e-12

@@ -118,3 +118,50 @@ def test_learned_plan_not_slower_than_greedy(C):
           % (res["greedy"][0], res["greedy"][1], res["learned"][0], res["learned"][1],
              100 * (1 - res["learned"][0] / res["greedy"][0])), flush=True)
     assert res["learned"][0] < res["greedy"][0]
+
+
+def test_layout_swap_from_the_model_runs_and_pays(C):
+    """N=30, dense 4-qubit gates alternating between qubits 20..23 and 0..3: the swap pass moves
+    20..23 down once; the run keeps the logical state (echo with the inverse plan back to |0...0>)
+    and takes less time than the plan without the swap.  Binding a plan with swaps is refused."""
+    import torch
+    import paper_2608_16940_amd as P
+    import paper_2608_16940_amd._native as N
+    params, _ = C.load()
+    n = 30
+    rng = np.random.default_rng(0)
+    gates = []
+    for _ in range(20):
+        gates.append(W.random_dense(n, 4, rng, (20, 21, 22, 23)))
+        gates.append(W.random_dense(n, 4, rng, (0, 1, 2, 3)))
+    base = P.Plan.greedy(n, gates, 4)
+    swp = P.Plan.greedy(n, gates, 4)
+    assert swp.add_swaps(params) == 1
+    sv = P.StateVector(n)
+
+    def timed(plan):
+        sv.reset()
+        plan.run(sv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            sv.reset()
+            plan.run(sv)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / 2
+    t_base, t_swap = timed(base), timed(swp)
+    print("alternating case: %.1f ms without swap, %.1f ms with the model's swap" % (t_base * 1e3, t_swap * 1e3),
+          flush=True)
+    assert t_swap < t_base
+    st = sv.stats()
+    assert st["permute_sweeps"] == 1
+    assert not np.array_equal(sv.layout(), np.arange(n))  # 20..23 now sit on the chosen window
+    inv = P.Plan.greedy(n, W.inverse(gates), 4)
+    inv.run(sv)
+    sv.sync()
+    f0 = abs(sv.amps[0].item()) ** 2 / sv.norm()
+    assert f0 >= 1 - 1e-5
+    with pytest.raises(P.SvError) as e:
+        swp.bind(sv)
+    assert e.value.code == N.SV_ERR_UNSUPPORTED
+    sv.close()
