@@ -77,8 +77,9 @@ def test_wide_blocks_against_oracle_samples(P, which, prec):
     idx, ref = read_golden()
     gates = W.brickwork(N, 16, 0)
     plan = plan_for(P, gates, which)
-    ks = [b["k"] for b in plan.blocks()]
-    dense_wide = sum(1 for b in plan.blocks() if b["k"] >= 5 and not b["diag"])
+    fused = [b for b in plan.blocks() if not b.get("swap")]  # layout swaps carry no matrix
+    ks = [b["k"] for b in fused]
+    dense_wide = sum(1 for b in fused if b["k"] >= 5 and not b["diag"])
     if which != "learned":
         assert max(ks) == which
     sv = P.StateVector(N)
