@@ -96,11 +96,25 @@ int sv_batch_prepared_free(sv_batch_prepared *p);
  *                           of following records in the pass; their qubit
  *                           numbers are slice bit positions (rank of the qubit
  *                           in the mask)
+ *   kind SV_BATCH_GATE_GROUP q0 = c (2..4): the next c records are
+ *                           single-qubit gates on distinct qubits that the
+ *                           kernel applies in one sweep (runs of consecutive
+ *                           single-qubit records, grouped by the host)
+ *   kind SV_BATCH_GATE_LINEAR (only inside passes) a run of q0 >= 3
+ *                           consecutive CNOTs as one linear map f on the 14
+ *                           slice bits: the slice becomes new[y] = old[f(y)],
+ *                           f(y) the XOR of mask[b] over the set bits b of y;
+ *                           masks 0..7 are the 8 float slots of this record
+ *                           and masks 8..13 the first 6 of the next record
+ *                           (kind SV_BATCH_GATE_LINEAR, q0 = -1), as int32
+ *                           bit patterns
  * records: int32[4 * cap], mats: float[8 * cap]; *n_out = records written.
- * cap >= 2 * c->n_gates always suffices.  Errors: SV_ERR_ARG (bad circuit,
+ * cap >= 3 * c->n_gates always suffices.  Errors: SV_ERR_ARG (bad circuit,
  * cap too small).
  */
 #define SV_BATCH_PASS 2
+#define SV_BATCH_GATE_GROUP 3
+#define SV_BATCH_GATE_LINEAR 4
 int sv_batch_records(const sv_batch_circuit *c, int cap, int32_t *records, float *mats, int *n_out);
 
 int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,

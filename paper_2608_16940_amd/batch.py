@@ -62,7 +62,7 @@ class Batch:
     def records(self, i: int):
         """Host only: the gate records the kernel runs for circuit i (after 1q fusion and slice passes)
         as (int32[m, 4] kind/q0/q1/0, float32[m, 8] 2x2 complex64 matrices)."""
-        cap = 2 * max(1, int(self.arr[i].n_gates)) + 2
+        cap = 3 * max(1, int(self.arr[i].n_gates)) + 2
         rec = np.zeros((cap, 4), dtype=np.int32)
         mats = np.zeros((cap, 8), dtype=np.float32)
         m = ctypes.c_int()

@@ -81,6 +81,116 @@ __device__ __forceinline__ void apply_gate(const BGate &G, float2 *st, int64_t d
   }
 }
 
+// A group record (kind SV_BATCH_GATE_GROUP, q0 = c in 2..4) is followed by c
+// single-qubit records on distinct qubits.  They commute, so one sweep
+// applies all of them: each thread holds the 2^c amplitudes of a group in
+// registers and applies every 2x2 factor there (one LDS read and write per
+// amplitude instead of c).
+template <int C>
+__device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int64_t dim, int lt, int Tc) {
+  int qs[C], srt[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) qs[j] = srt[j] = M[j].q0;
+#pragma unroll
+  for (int i = 1; i < C; ++i)
+#pragma unroll
+    for (int j = C - 1; j >= i; --j)
+      if (srt[j - 1] > srt[j]) {
+        const int t = srt[j];
+        srt[j] = srt[j - 1];
+        srt[j - 1] = t;
+      }
+  for (int64_t p = lt; p < (dim >> C); p += Tc) {
+    int64_t base = p;
+#pragma unroll
+    for (int j = 0; j < C; ++j) base = ins0(base, srt[j]);
+    float2 a[1 << C];
+#pragma unroll
+    for (int t = 0; t < (1 << C); ++t) {
+      int64_t o = 0;
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if ((t >> j) & 1) o |= int64_t(1) << qs[j];
+      a[t] = st[base + o];
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const float *m = M[j].m;
+#pragma unroll
+      for (int t = 0; t < (1 << C); ++t) {
+        if ((t >> j) & 1) continue;
+        const float2 x = a[t], y = a[t | (1 << j)];
+        float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
+        o0 = cmad(m[0], m[1], x, o0);
+        o0 = cmad(m[2], m[3], y, o0);
+        o1 = cmad(m[4], m[5], x, o1);
+        o1 = cmad(m[6], m[7], y, o1);
+        a[t] = o0;
+        a[t | (1 << j)] = o1;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < (1 << C); ++t) {
+      int64_t o = 0;
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+        if ((t >> j) & 1) o |= int64_t(1) << qs[j];
+      st[base + o] = a[t];
+    }
+  }
+}
+
+// A linear record (kind SV_BATCH_GATE_LINEAR, only inside passes, where one
+// workgroup runs one circuit) replaces a run of CNOTs on slice bits: the run
+// maps the amplitude at y to the one at f(y), f linear over GF(2), so the new
+// slice is new[y] = old[f(y)] with f(y) the XOR of mask[b] over the set bits
+// b of y.  The 14 masks ride in the float slots of the record and of the one
+// after it.  Every thread gathers its 32 amplitudes, the workgroup meets a
+// barrier, then every thread writes them back: one LDS sweep for the run.
+__device__ __forceinline__ void apply_linear(const BGate *R, float2 *lds, int tid) {
+  constexpr int PER = kLdsAmps / kBT;  // 32 amplitudes per thread: y = tid + kBT * i
+  int32_t mk[kSliceBits];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) mk[b] = __float_as_int(R[0].m[b]);
+#pragma unroll
+  for (int b = 8; b < kSliceBits; ++b) mk[b] = __float_as_int(R[1].m[b - 8]);
+  int32_t ft = 0;  // f(tid): tid covers the low 9 bits of y
+#pragma unroll
+  for (int b = 0; b < 9; ++b)
+    if ((tid >> b) & 1) ft ^= mk[b];
+  float2 v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    int32_t fi = ft;  // i covers the high 5 bits
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+      if ((i >> b) & 1) fi ^= mk[9 + b];
+    v[i] = lds[fi];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) lds[tid + kBT * i] = v[i];
+}
+static_assert(kLdsAmps == kBT << 5 && kSliceBits == 14, "linear records assume 2^14 slices over 512 threads");
+
+// One unit at record r (a gate, a group header and its members, or a linear
+// record and its mask record); returns the number of records it spans.
+__device__ __forceinline__ int apply_unit(const BGate *R, float2 *st, int64_t dim, int lt, int Tc) {
+  if (R[0].kind == SV_BATCH_GATE_LINEAR) {
+    apply_linear(R, st, lt);  // only in passes: dim = kLdsAmps, Tc = kBT
+    return 2;
+  }
+  if (R[0].kind == SV_BATCH_GATE_GROUP) {
+    const int c = R[0].q0;
+    if (c == 2) apply_group_c<2>(R + 1, st, dim, lt, Tc);
+    else if (c == 3) apply_group_c<3>(R + 1, st, dim, lt, Tc);
+    else apply_group_c<4>(R + 1, st, dim, lt, Tc);
+    return 1 + c;
+  }
+  apply_gate(R[0], st, dim, lt, Tc);
+  return 1;
+}
+
 __global__ void k_batch_reset(unsigned *counter) {
   if (threadIdx.x == 0) *counter = 0u;
 }
@@ -112,12 +222,11 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
     for (int64_t x = lt; x < dim; x += Tc) st[x] = make_float2(x == 0 ? 1.f : 0.f, 0.f);
     __syncthreads();
     if (in_lds) {
-      // lockstep over the pack: a circuit past its last gate only meets the barriers
+      // lockstep over the pack, one unit (gate or group) per step: a circuit
+      // past its last unit only meets the barriers
+      int r = 0;  // this circuit's next record
       for (int g = 0; g < ngates; ++g) {
-        BGate G;
-        G.kind = -1;
-        if (g < my_ng) G = gl[g];
-        apply_gate(G, st, dim, lt, Tc);
+        if (g < my_ng) r += apply_unit(gl + r, st, dim, lt, Tc);
         __syncthreads();
       }
     } else {
@@ -151,8 +260,8 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
           }
           for (int x = tid; x < kLdsAmps; x += kBT) lds[x] = st[base + offlo[x & 127] + offhi[x >> 7]];
           __syncthreads();
-          for (int j = 1; j <= cnt; ++j) {
-            apply_gate(gl[g + j], lds, kLdsAmps, tid, kBT);
+          for (int j = 1; j <= cnt;) {
+            j += apply_unit(gl + g + j, lds, kLdsAmps, tid, kBT);
             __syncthreads();
           }
           for (int x = tid; x < kLdsAmps; x += kBT) st[base + offlo[x & 127] + offhi[x >> 7]] = lds[x];
@@ -268,6 +377,98 @@ std::vector<BGate> make_passes(const std::vector<BGate> &g, int n) {
   return out;
 }
 
+// Runs of up to four consecutive single-qubit records on distinct qubits
+// become one group (a header, then the members).  Within a pass list (after
+// make_passes) only the gates inside each pass are grouped and the pass
+// header's record count follows.
+std::vector<BGate> group_run(const std::vector<BGate> &g, size_t a, size_t b) {
+  std::vector<BGate> out;
+  size_t i = a;
+  while (i < b) {
+    size_t j = i;
+    uint32_t used = 0;
+    while (j < b && j - i < 4 && g[j].kind == SV_BATCH_GATE_1Q && !((used >> g[j].q0) & 1u)) {
+      used |= 1u << g[j].q0;
+      ++j;
+    }
+    if (j - i >= 2) {
+      BGate h;
+      std::memset(&h, 0, sizeof(h));
+      h.kind = SV_BATCH_GATE_GROUP;
+      h.q0 = int32_t(j - i);
+      out.push_back(h);
+      out.insert(out.end(), g.begin() + long(i), g.begin() + long(j));
+      i = j;
+    } else {
+      out.push_back(g[i]);
+      ++i;
+    }
+  }
+  return out;
+}
+
+// Runs of three or more consecutive CNOT records inside a pass (slice bit
+// positions) become one linear record and its mask record.  A CNOT maps the
+// amplitude at y to the one at g(y) = y ^ (bit c of y) << t; the run
+// g_1 .. g_m (g_1 applied first) gives new[y] = old[g_1(g_2(... g_m(y)))],
+// whose value on each basis vector e_b is mask[b].
+std::vector<BGate> merge_cnots(const std::vector<BGate> &g, size_t a, size_t b) {
+  std::vector<BGate> out;
+  size_t i = a;
+  while (i < b) {
+    size_t j = i;
+    while (j < b && g[j].kind == SV_BATCH_GATE_CNOT) ++j;
+    if (j - i >= 3) {
+      int32_t mk[kSliceBits];
+      for (int bit = 0; bit < kSliceBits; ++bit) {
+        int32_t y = int32_t(1) << bit;
+        for (size_t r = j; r-- > i;) y ^= ((y >> g[r].q0) & 1) << g[r].q1;
+        mk[bit] = y;
+      }
+      BGate h, d;
+      std::memset(&h, 0, sizeof(h));
+      std::memset(&d, 0, sizeof(d));
+      h.kind = SV_BATCH_GATE_LINEAR;
+      h.q0 = int32_t(j - i);  // CNOTs replaced (informational)
+      d.kind = SV_BATCH_GATE_LINEAR;
+      d.q0 = -1;  // the mask record
+      for (int bit = 0; bit < 8; ++bit) std::memcpy(&h.m[bit], &mk[bit], 4);
+      for (int bit = 8; bit < kSliceBits; ++bit) std::memcpy(&d.m[bit - 8], &mk[bit], 4);
+      out.push_back(h);
+      out.push_back(d);
+      i = j;
+    } else {
+      for (; i < j; ++i) out.push_back(g[i]);
+      if (i < b && g[i].kind != SV_BATCH_GATE_CNOT) out.push_back(g[i++]);
+    }
+  }
+  return out;
+}
+
+std::vector<BGate> group_single_qubit(const std::vector<BGate> &g, bool passes) {
+  if (!passes) return group_run(g, 0, g.size());
+  std::vector<BGate> out;
+  size_t i = 0;
+  while (i < g.size()) {
+    const size_t cnt = size_t(g[i].q1);
+    std::vector<BGate> merged = merge_cnots(g, i + 1, i + 1 + cnt);
+    std::vector<BGate> body = group_run(merged, 0, merged.size());
+    BGate h = g[i];
+    h.q1 = int32_t(body.size());
+    out.push_back(h);
+    out.insert(out.end(), body.begin(), body.end());
+    i += 1 + cnt;
+  }
+  return out;
+}
+
+// Units (a gate, or a group with its members) in a record list without passes.
+int count_units(const std::vector<BGate> &g) {
+  int u = 0;
+  for (size_t i = 0; i < g.size(); i += (g[i].kind == SV_BATCH_GATE_GROUP) ? 1 + size_t(g[i].q0) : 1) ++u;
+  return u;
+}
+
 bool valid_config(const int32_t *cfg) {
   for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
     const int P = cfg[n];
@@ -364,6 +565,7 @@ int pack_batch(int count, const sv_batch_circuit *circs, size_t states_bytes, co
     }
     flush();
     if (C.n_qubits > kSliceBits) g = make_passes(g, C.n_qubits);
+    g = group_single_qubit(g, C.n_qubits > kSliceBits);
     groups[C.n_qubits].push_back(i);
   }
   out->ncirc = count;
@@ -390,7 +592,8 @@ int pack_batch(int count, const sv_batch_circuit *circs, size_t states_bytes, co
       for (int c = 0; c < P; ++c) {
         const int id = ids[pos + size_t(c)];
         it.circ[c] = id;
-        it.ngc[c] = int(fused[size_t(id)].size());
+        // records for a circuit run in passes, units for one held in LDS
+        it.ngc[c] = (n > kSliceBits) ? int(fused[size_t(id)].size()) : count_units(fused[size_t(id)]);
         ng = std::max(ng, it.ngc[c]);
         it.gate_off[c] = gate_off[size_t(id)];
         it.state_off[c] = state_offsets[id] / 8;
@@ -490,8 +693,8 @@ extern "C" {
 
 size_t sv_batch_workspace_bytes(int count, const sv_batch_circuit *circs) {
   if (count < 0 || (count > 0 && !circs)) return 0;
-  size_t ng = 0;  // at most one pass record per gate on top of the gates
-  for (int i = 0; i < count; ++i) ng += 2 * size_t(std::max(0, circs[i].n_gates));
+  size_t ng = 0;  // at most one pass record and half a group record per gate on top of the gates
+  for (int i = 0; i < count; ++i) ng += 3 * size_t(std::max(0, circs[i].n_gates));
   return 256 + align256(sizeof(double) * size_t(std::max(1, count))) +
          align256(sizeof(BItem) * size_t(std::max(1, count))) + align256(sizeof(BGate) * std::max<size_t>(1, ng));
 }

@@ -40,6 +40,8 @@ def apply_cnot(v, c, t_, nb):
 
 
 def apply_record(v, rec, mat, nb):
+    if rec[0] == 3:
+        return  # group header: its members follow as single-qubit records on distinct qubits (they commute)
     if rec[0] == 0:
         m = mat.astype(np.float64).view(np.complex128).reshape(2, 2)
         apply_1q(v, int(rec[1]), m, nb)
@@ -72,9 +74,21 @@ def replay(n, recs, mats):
             for r, q in enumerate(rest):
                 base |= ((sl >> r) & 1) << q
             v = psi[base + local].copy()
-            for r, m in zip(recs[i + 1:i + 1 + cnt], mats[i + 1:i + 1 + cnt]):
-                assert 0 <= r[1] < SLICE and (r[0] != 1 or 0 <= r[2] < SLICE)
-                apply_record(v, r, m, SLICE)
+            j = i + 1
+            while j < i + 1 + cnt:
+                r = recs[j]
+                if r[0] == 4:  # a run of CNOTs as one linear map: new[y] = old[f(y)]
+                    masks = np.concatenate([mats[j].view(np.int32), mats[j + 1][:6].view(np.int32)])
+                    y = np.arange(1 << SLICE)
+                    f = np.zeros_like(y)
+                    for b in range(SLICE):
+                        f ^= np.where((y >> b) & 1, masks[b], 0)
+                    v = v[f].copy()
+                    j += 2
+                    continue
+                assert r[0] == 3 or (0 <= r[1] < SLICE and (r[0] != 1 or 0 <= r[2] < SLICE))
+                apply_record(v, r, mats[j], SLICE)
+                j += 1
             psi[base + local] = v
         i += 1 + cnt
         passes += 1
@@ -106,9 +120,15 @@ def test_records_replay_equals_oracle(B, n, depth, reverse):
     ref = oracle.run(n, gates)
     m = oracle.metrics(ref, got)
     assert m["infidelity"] <= 1e-10 and m["max_abs"] <= 1e-6, m
-    ops = [r for r in recs if r[0] != 2]
-    # RY and RZ on the same qubit fuse into one single-qubit record
-    assert len(ops) == depth * n + sum(1 for g in gates if g.kind == "cnot")
+    ops = [r for r in recs if r[0] in (0, 1)]
+    groups = [r for r in recs if r[0] == 3]
+    assert groups and all(2 <= g[1] <= 4 for g in groups)  # layers of rotations run as groups
+    linear = [r for r in recs if r[0] == 4 and r[1] >= 3]  # runs of CNOTs merged (passes only)
+    assert all(r[1] != -1 for r in linear)
+    # RY and RZ on the same qubit fuse into one single-qubit record; every CNOT is a record or in a run
+    assert len(ops) + sum(int(r[1]) for r in linear) == depth * n + sum(1 for g in gates if g.kind == "cnot")
+    if n > SLICE:
+        assert linear
     if n > SLICE:
         assert 1 <= passes <= len(ops)
     else:
