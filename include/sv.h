@@ -134,6 +134,15 @@ int sv_sample(sv_state *s, uint64_t seed, int64_t shots, uint64_t *out_host);
 int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots, uint64_t *out_host,
                     void *ws_dev, size_t ws_bytes, void *stream);
 
+/*
+ * Copy the state to caller-owned host memory (out_host >= 8 * 2^N bytes,
+ * complex64 interleaved).  logical_order = 0: physical order, as stored;
+ * 1: logical basis order, out[x] = amps[y] with y_{L(q)} = x_q (decoded on the
+ * host: the layout and the device state are left as they are).  Waits for the
+ * handle's stream first.  Errors: SV_ERR_ARG (null), SV_ERR_DEVICE.
+ */
+int sv_copy_out(sv_state *s, void *out_host, int logical_order);
+
 /* Wait for all work enqueued by this handle. */
 int sv_sync(sv_state *s);
 

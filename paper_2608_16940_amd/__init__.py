@@ -145,6 +145,12 @@ class StateVector:
         a = np.ascontiguousarray(np.asarray(next_use, dtype=np.int64))
         check(lib().sv_hint_next_use(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
 
+    def copy_out(self, logical: bool = True) -> np.ndarray:
+        """Host complex64 copy of the state (sv_copy_out): logical basis order, or physical order."""
+        out = np.empty(1 << self.n, dtype=np.complex64)
+        check(lib().sv_copy_out(self._h, out.ctypes.data_as(ctypes.c_void_p), 1 if logical else 0))
+        return out
+
     def physical_state(self) -> np.ndarray:
         """Host copy of the stored amplitudes (physical order), complex128."""
         self.sync()

@@ -73,6 +73,7 @@ SIGNATURES = [
     ("sv_sample_probs", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, _u64p, _vp,
                                        ctypes.c_size_t, _vp]),
     ("sv_sync", ctypes.c_int, [_vp]),
+    ("sv_copy_out", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     ("sv_dm_state_bytes", ctypes.c_size_t, [ctypes.c_int]),
     ("sv_dm_workspace_bytes", ctypes.c_size_t, [ctypes.c_int]),
     ("sv_dm_alloc", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t,

@@ -732,6 +732,32 @@ int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots
   return sample_impl(nullptr, probs_dev, n, ws, seed, shots, out_host, L, static_cast<hipStream_t>(stream));
 }
 
+int sv_copy_out(sv_state *s, void *out_host, int logical_order) {
+  if (!s || !out_host) {
+    set_error("null pointer");
+    return SV_ERR_ARG;
+  }
+  const int n = s->n;
+  const size_t dim = size_t(1) << n;
+  SV_HIP_CHECK(hipStreamSynchronize(s->st));
+  if (!logical_order) {
+    SV_HIP_CHECK(hipMemcpy(out_host, s->amps, dim * sizeof(float2), hipMemcpyDeviceToHost));
+    return SV_OK;
+  }
+  std::vector<float2> phys(dim);
+  SV_HIP_CHECK(hipMemcpy(phys.data(), s->amps, dim * sizeof(float2), hipMemcpyDeviceToHost));
+  float2 *out = static_cast<float2 *>(out_host);
+  // y(x) = sum over set bits q of x of 2^L(q), built from the lowest set bit up
+  std::vector<uint64_t> bitpos(static_cast<size_t>(n));
+  for (int q = 0; q < n; ++q) bitpos[size_t(q)] = uint64_t(1) << s->L[q];
+  for (size_t x = 0; x < dim; ++x) {
+    uint64_t y = 0;
+    for (size_t r = x; r; r &= r - 1) y |= bitpos[size_t(__builtin_ctzll(r))];
+    out[x] = phys[size_t(y)];
+  }
+  return SV_OK;
+}
+
 int sv_sync(sv_state *s) {
   if (!s) {
     set_error("null handle");

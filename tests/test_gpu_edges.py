@@ -80,3 +80,24 @@ def test_gate_over_every_qubit(P, n):
     shots = sv.sample(11, 500)
     np.testing.assert_array_equal(shots, oracle.sample(p, 11, 500))
     sv.close()
+
+
+def test_copy_out_physical_and_logical(P):
+    """sv_copy_out: physical order is the stored state; logical order decodes y_{L(q)} = x_q on the host
+    and leaves the layout and the device state unchanged."""
+    n = 14
+    rng = np.random.default_rng(14)
+    gates = [W.random_dense(n, k, rng) for k in (1, 2, 3, 5, 2)]
+    sv = P.StateVector(n)
+    for g in gates:
+        sv.apply(g.matrix, g.targets)
+    perm = rng.permutation(n).astype(np.int32)
+    sv.permute_layout(perm)
+    phys = sv.copy_out(logical=False)
+    np.testing.assert_array_equal(phys, sv.amps.cpu().numpy())
+    log = sv.copy_out(logical=True)
+    np.testing.assert_array_equal(log.astype(np.complex128), oracle.decode(phys.astype(np.complex128), perm))
+    assert list(sv.layout()) == list(perm)
+    m = oracle.metrics(oracle.run(n, gates), log.astype(np.complex128))
+    assert m["infidelity"] < 1e-5 and m["max_abs"] < 1e-5
+    sv.close()
