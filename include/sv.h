@@ -186,10 +186,9 @@ const char *sv_last_error(void);
 #define SV_POLICY_LRU 2        /* least recently used qubit */
 
 /* Where the waves of an MFMA sweep read the gate operand: their own
- * registers (k <= 5), once per workgroup in LDS (k <= 6; FP32 k = 7), or
- * from global memory through the caches (k >= 5).  AUTO (default) takes the
- * placement measured fastest for each width and precision (LDS except for
- * BF16x3 k = 7);
+ * registers (k <= 5), once per workgroup in LDS (k <= 7), or from global
+ * memory through the caches (k >= 5).  AUTO (default) takes the placement
+ * measured fastest for each width and precision (LDS);
  * kernels without the requested placement use their AUTO choice. */
 #define SV_OPT_MFMA_OPERAND 6
 #define SV_MFMA_OPERAND_REGS 0

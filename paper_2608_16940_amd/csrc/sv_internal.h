@@ -97,7 +97,8 @@ struct TilePlan {
 };
 
 // Real-embedded, lane-major MFMA operand for gate matrix G (FP64 host, 2^K x 2^K).
-// prec = SV_PREC_FP32: float; SV_PREC_BF16X3: uint16 hi then lo planes.
+// prec = SV_PREC_FP32: float; SV_PREC_BF16X3: uint16 (k = 4: embedding hi then lo;
+// k >= 5: Gr hi, Gr lo, Gi hi, Gi lo planes).
 size_t mfma_operand_bytes(int K, int prec);
 void pack_mfma_operand(int K, int prec, const double *G, void *out);
 

@@ -18,9 +18,14 @@
 //       Re y = T1 - T2, Im y = T3 - T1 - T2,
 //     three 2^K x 2^K real GEMMs, 25% fewer MFMA cycles than the embedding;
 //     only Gr and Gi are stored, Gr + Gi is one VALU add per step;
-//   * BF16x3 (any k): the embedding with each operand split x = hi + lo in
-//     bf16 and hi*hi + hi*lo + lo*hi accumulated in FP32
-//     (v_mfma_f32_32x32x8bf16_1k); G is split once on the host from FP64.
+//   * BF16x3: each operand split x = hi + lo in bf16 and hi*hi + hi*lo +
+//     lo*hi accumulated in FP32; G is split once on the host from FP64.  At
+//     k = 4 the real embedding on v_mfma_f32_32x32x8bf16_1k (16 output rows
+//     fill a 32-row tile only when embedded); at k >= 5 the four real GEMMs
+//       Re y = Gr Xr - Gi Xi,  Im y = Gi Xr + Gr Xi
+//     on gfx950's v_mfma_f32_32x32x16_bf16 (twice the rate of the 32x32x8
+//     form), with only the Gr and Gi planes stored (half the embedding's
+//     bytes) and -Xi formed by flipping sign bits.
 //
 // Operand layout.  The reduction ordering is free, so lane l of a wave holds
 // group (l mod 32) and the contiguous half h = l / 32 of its inputs; MFMA step
@@ -45,6 +50,15 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ floatx16 mfma_bf16x16(uint4 a, uint4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                  0, 0);
+}
+__device__ __forceinline__ uint4 flip_sign(uint4 x) {
+  return make_uint4(x.x ^ 0x80008000u, x.y ^ 0x80008000u, x.z ^ 0x80008000u, x.w ^ 0x80008000u);
+}
 
 // Amplitudes are touched exactly once per sweep: stream them with
 // non-temporal loads and stores so they do not displace cached operands.
@@ -108,13 +122,14 @@ __device__ __forceinline__ uint2 bf16x3_split(float re, float im) {
 // memory through the caches (read per MFMA; only for the widest gates).
 enum OpSrc { OP_REG = 0, OP_LDS = 1, OP_GLOBAL = 2 };
 // Arithmetic scheme.
-enum Alg { ALG_EMBED_F32 = 0, ALG_GAUSS_F32 = 1, ALG_EMBED_BF16X3 = 2 };
+enum Alg { ALG_EMBED_F32 = 0, ALG_GAUSS_F32 = 1, ALG_EMBED_BF16X3 = 2, ALG_CPLX_BF16X3 = 3 };
 
 template <int K, int PREC>
 struct Scheme {
-  static constexpr int alg = (PREC == SV_PREC_BF16X3) ? ALG_EMBED_BF16X3 : (K >= 5 ? ALG_GAUSS_F32 : ALG_EMBED_F32);
-  // operand bytes (see pack_mfma_operand)
-  static constexpr int bytes = (alg == ALG_GAUSS_F32) ? 2 * (1 << (2 * K + 2)) : (1 << (2 * K + 4));
+  static constexpr int alg = (PREC == SV_PREC_BF16X3) ? (K >= 5 ? ALG_CPLX_BF16X3 : ALG_EMBED_BF16X3)
+                                                      : (K >= 5 ? ALG_GAUSS_F32 : ALG_EMBED_F32);
+  // operand bytes (see pack_mfma_operand): two FP32 planes, four bf16 planes, or the embedding
+  static constexpr int bytes = (alg == ALG_GAUSS_F32 || alg == ALG_CPLX_BF16X3) ? (1 << (2 * K + 3)) : (1 << (2 * K + 4));
 };
 
 // Occupancy target (waves per SIMD the register budget is cut for).  FP32
@@ -127,11 +142,12 @@ struct WavesPerSimd {
 };
 
 // Register prefetch of the next tile: measured at N=30 on MI355X, FP32 k=6
-// 6.0 -> 4.1 ms, FP32 k=7 10.2 -> 9.7 ms, BF16x3 k=6 5.5 -> 5.3 ms; BF16x3 k=7
-// and the memory-bound k <= 5 sweeps are as fast or faster without it.
+// 6.0 -> 4.1 ms, FP32 k=7 10.2 -> 9.7 ms, BF16x3 k=6 5.5 -> 5.3 ms, BF16x3 k=7
+// (complex form, operand in LDS, one workgroup per CU) 4.3 -> 3.8 ms; the
+// memory-bound k <= 5 sweeps are as fast or faster without it.
 template <int K, int PREC>
 struct Prefetch {
-  static constexpr bool value = K >= 6 && !(PREC == SV_PREC_BF16X3 && K == 7);
+  static constexpr bool value = K >= 6;
 };
 constexpr int kPrefetchGridPerCU = 16;
 
@@ -146,7 +162,8 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   constexpr int NOPF = Scheme<K, PREC>::bytes / 4;  // operand size in floats
   constexpr int HALF = 1 << K;           // embedding: reals per lane half
   constexpr int KQ = HALF / 4;
-  constexpr int MTT = (ALG == ALG_GAUSS_F32) ? (1 << K) / 32 : (2 << K) / 32;  // 32-row output tiles
+  constexpr bool CPLX_ROWS = (ALG == ALG_GAUSS_F32 || ALG == ALG_CPLX_BF16X3);  // output rows are amplitudes
+  constexpr int MTT = CPLX_ROWS ? (1 << K) / 32 : (2 << K) / 32;  // 32-row output tiles
   constexpr int NCB = (1 << M) / 32;     // 32-group column blocks per tile
   static_assert(MTT * NCB >= 4 && (MTT * NCB) % 4 == 0, "four waves share the (block, tile) pairs");
   constexpr int MPW = MTT * NCB / 4;     // output tiles per wave
@@ -154,12 +171,13 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   // BF16x3 k >= 6: the cross terms hi*lo and lo*hi accumulate apart from
   // hi*hi (two independent MFMA chains per output tile; 5-10% faster at N=30,
   // a third set costs occupancy); summed in FP32 before the store
-  constexpr int BSETS = (ALG == ALG_EMBED_BF16X3 && K >= 6) ? 2 : 1;
-  constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * MPW : BSETS * MPW;
+  constexpr int BSETS = ((ALG == ALG_EMBED_BF16X3 || ALG == ALG_CPLX_BF16X3) && K >= 6) ? 2 : 1;
+  constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * MPW : (ALG == ALG_CPLX_BF16X3 ? 2 : 1) * BSETS * MPW;
   // BF16x3 k = 6: split the inputs into hi/lo once as the tile lands in LDS
   // (two waves read every group; measured 4% faster at N=30); k = 5 and 7
   // measured 1-3% slower that way and split inside the product loop
-  constexpr bool SPLIT_AT_LOAD = (ALG == ALG_EMBED_BF16X3 && K == 6);
+  // and always in the complex form, whose B operands gather 8 amplitudes' halves
+  constexpr bool SPLIT_AT_LOAD = (ALG == ALG_EMBED_BF16X3 && K == 6) || ALG == ALG_CPLX_BF16X3;
   __shared__ float2 lds[TILE];
   __shared__ float opl_s[OPS == OP_LDS ? NOPF : 1];
 
@@ -190,7 +208,18 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   float ra[NREG];
   (void)ra;
   if constexpr (OPS == OP_REG) {
-    if constexpr (ALG == ALG_EMBED_BF16X3) {
+    if constexpr (ALG == ALG_CPLX_BF16X3) {
+      // 16 bytes (eight bf16) per lane and unit
+      const float4 *op4 = reinterpret_cast<const float4 *>(a.op);
+#pragma unroll
+      for (int i = 0; i < NREG / 4; ++i) {
+        const float4 t = op4[i * 64 + lane];
+        ra[4 * i] = t.x;
+        ra[4 * i + 1] = t.y;
+        ra[4 * i + 2] = t.z;
+        ra[4 * i + 3] = t.w;
+      }
+    } else if constexpr (ALG == ALG_EMBED_BF16X3) {
       // the bf16 operand holds one 8-byte group of four per lane: floats (2i, 2i + 1) of this lane
       const float2 *op2 = reinterpret_cast<const float2 *>(a.op);
 #pragma unroll
@@ -322,7 +351,7 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
         for (int e = 0; e < 8; ++e)
           lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[j][2 * e], acc[j][2 * e + 1]);
       }
-    } else {
+    } else if constexpr (ALG == ALG_EMBED_BF16X3) {
       const shortx4 *oph = reinterpret_cast<const shortx4 *>(opsrc);
       // fully unrolled up to k = 5, and at k = 6 with the operand in LDS (6.5%
       // faster than 4 steps at N=30); k = 7 (operand through the caches) is
@@ -378,6 +407,73 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[j][2 * e], acc[j][2 * e + 1]);
+      }
+    } else {
+      // complex form: step kk reduces over amplitudes AH h + 8 kk + e (e < 8) of this
+      // lane's group; operand unit ((P MTT + mt) KS + kk) holds plane P in
+      // (Gr hi, Gr lo, Gi hi, Gi lo) for those eight columns
+      constexpr int KS = AH / 8;
+      constexpr int UNR = (OPS == OP_LDS && K >= 6) ? KS : (K == 5 ? 1 : 2);  // wider unrolls spill
+      constexpr int XS = (BSETS - 1) * MPW;  // cross-term accumulator offset
+      floatx16 *accR = acc, *accI = acc + BSETS * MPW;
+      const uint2 *ldsu = reinterpret_cast<const uint2 *>(lds);
+      auto opq = [&](int q) -> uint4 {
+        if constexpr (OPS == OP_REG)
+          return make_uint4(__float_as_uint(ra[4 * q]), __float_as_uint(ra[4 * q + 1]), __float_as_uint(ra[4 * q + 2]),
+                            __float_as_uint(ra[4 * q + 3]));
+        else
+          return reinterpret_cast<const uint4 *>(opsrc)[q * 64 + lane];
+      };
+#pragma unroll UNR
+      for (int kk = 0; kk < KS; ++kk) {
+        uint2 sl[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sl[e] = ldsu[swz<K>(gbase | (h * AH + 8 * kk + e))];
+        // slot = (hi re | hi im << 16, lo re | lo im << 16): gather each half of eight amplitudes
+        uint32_t rh[4], ih[4], rl[4], il[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const uint2 a0 = sl[2 * p], a1 = sl[2 * p + 1];
+          rh[p] = (a0.x & 0xFFFFu) | (a1.x << 16);
+          ih[p] = (a0.x >> 16) | (a1.x & 0xFFFF0000u);
+          rl[p] = (a0.y & 0xFFFFu) | (a1.y << 16);
+          il[p] = (a0.y >> 16) | (a1.y & 0xFFFF0000u);
+        }
+        const uint4 xrh = make_uint4(rh[0], rh[1], rh[2], rh[3]), xih = make_uint4(ih[0], ih[1], ih[2], ih[3]);
+        const uint4 xrl = make_uint4(rl[0], rl[1], rl[2], rl[3]), xil = make_uint4(il[0], il[1], il[2], il[3]);
+        const uint4 nxih = flip_sign(xih), nxil = flip_sign(xil);
+#pragma unroll
+        for (int j = 0; j < MPW; ++j) {
+          const int mt = mt0 + j * MT_STEP;
+          const uint4 grh = opq((0 * MTT + mt) * KS + kk), grl = opq((1 * MTT + mt) * KS + kk);
+          const uint4 gih = opq((2 * MTT + mt) * KS + kk), gil = opq((3 * MTT + mt) * KS + kk);
+          accR[j] = mfma_bf16x16(grh, xrh, accR[j]);
+          accI[j] = mfma_bf16x16(gih, xrh, accI[j]);
+          accR[j] = mfma_bf16x16(gih, nxih, accR[j]);
+          accI[j] = mfma_bf16x16(grh, xih, accI[j]);
+          accR[XS + j] = mfma_bf16x16(grh, xrl, accR[XS + j]);
+          accI[XS + j] = mfma_bf16x16(gih, xrl, accI[XS + j]);
+          accR[XS + j] = mfma_bf16x16(grl, xrh, accR[XS + j]);
+          accI[XS + j] = mfma_bf16x16(gil, xrh, accI[XS + j]);
+          accR[XS + j] = mfma_bf16x16(gih, nxil, accR[XS + j]);
+          accI[XS + j] = mfma_bf16x16(grh, xil, accI[XS + j]);
+          accR[XS + j] = mfma_bf16x16(gil, nxih, accR[XS + j]);
+          accI[XS + j] = mfma_bf16x16(grl, xih, accI[XS + j]);
+        }
+      }
+      if constexpr (SHARED_GROUPS) __syncthreads();
+#pragma unroll
+      for (int j = 0; j < MPW; ++j) {
+        const int mt = mt0 + j * MT_STEP;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float re = accR[j][r], im = accI[j][r];
+          if constexpr (BSETS > 1) {
+            re += accR[XS + j][r];
+            im += accI[XS + j][r];
+          }
+          lds[swz<K>(gbase | (h * AH + 16 * mt + r))] = make_float2(re, im);
+        }
       }
     }
     __syncthreads();
@@ -650,8 +746,9 @@ bool make_gate_tile(int n, int K, const int32_t *A, uint64_t extra, TilePlan *tp
 }
 
 size_t mfma_operand_bytes(int K, int prec) {
-  if (prec == SV_PREC_FP32 && K >= 5) return size_t(2) << (2 * K + 2);
-  return size_t(1) << (2 * K + 4);
+  (void)prec;
+  if (K >= 5) return size_t(1) << (2 * K + 3);  // FP32 Gr, Gi or bf16 Gr, Gi hi and lo
+  return size_t(1) << (2 * K + 4);              // the real embedding (FP32, or bf16 hi and lo)
 }
 
 void pack_mfma_operand(int K, int prec, const double *G, void *out) {
@@ -679,6 +776,24 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out) {
       for (int kk = 0; kk < HALF; ++kk)
         for (int l = 0; l < 64; ++l)
           o[(mt * HALF + kk) * 64 + l] = float(embedded(G, K, out_row(HALF, mt, l & 31), HALF * (l >> 5) + kk));
+  } else if (K >= 5) {
+    // BF16x3 complex form: planes (Gr hi, Gr lo, Gi hi, Gi lo) of the split
+    // (split_bf16x3); plane P, tile mt, step kk, lane l holds the eight bf16
+    // P[out_row(AH, mt, l % 32)][AH * (l / 32) + 8 kk + e], e < 8
+    const int GMT = D / 32, KS = AH / 8;
+    uint16_t *o = static_cast<uint16_t *>(out);
+    std::vector<uint16_t> sp(4 * size_t(D) * D);
+    uint16_t *hr = sp.data(), *lr = hr + D * D, *hm = lr + D * D, *lm = hm + D * D;
+    split_bf16x3(D, G, hr, lr, hm, lm);
+    const uint16_t *plane[4] = {hr, lr, hm, lm};
+    for (int P = 0; P < 4; ++P)
+      for (int mt = 0; mt < GMT; ++mt)
+        for (int kk = 0; kk < KS; ++kk)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+              const int r = out_row(AH, mt, l & 31), c = AH * (l >> 5) + 8 * kk + e;
+              o[((((size_t(P) * GMT + mt) * KS + kk) * 64) + l) * 8 + e] = plane[P][r * D + c];
+            }
   } else {
     // embedding [[Re, -Im], [Im, Re]] of the split planes (split_bf16x3), hi
     // and lo planes; four consecutive reductions per step
@@ -713,8 +828,8 @@ void pack_mfma_operand(int K, int prec, const double *G, void *out) {
 hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi, const void *op, hipStream_t st) {
   const bool bf = (prec == SV_PREC_BF16X3);
   int o = opsrc;
-  if (o == SV_MFMA_OPERAND_AUTO)  // measured at N=30 on MI355X: LDS up to k=6 and FP32 k=7, caches for BF16 k=7
-    o = (tp.K <= 6 || !bf) ? SV_MFMA_OPERAND_LDS : SV_MFMA_OPERAND_GLOBAL;
+  if (o == SV_MFMA_OPERAND_AUTO)  // measured at N=30 on MI355X: LDS for every width (BF16x3 k=7: 3.8 vs 4.2 ms)
+    o = SV_MFMA_OPERAND_LDS;
   switch (tp.K) {
     case 4:
       if (o == SV_MFMA_OPERAND_REGS) return bf ? tile_mfma_k<4, 7, SV_PREC_BF16X3, OP_REG>(tp, psi, op, st) : tile_mfma_k<4, 7, SV_PREC_FP32, OP_REG>(tp, psi, op, st);
@@ -726,9 +841,10 @@ hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi
     case 6:  // no register form: REGS takes the automatic choice (LDS)
       if (o != SV_MFMA_OPERAND_GLOBAL) return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
       return bf ? tile_mfma_k<6, 6, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<6, 6, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
-    case 7:  // FP32: the two 64 KiB operand planes and the 32 KiB tile fill the 160 KiB of LDS;
-             // BF16x3 (256 KiB operand) always reads through the caches; REGS takes the automatic choice
-      if (!bf && o != SV_MFMA_OPERAND_GLOBAL) return tile_mfma_k<7, 5, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
+    case 7:  // the two 64 KiB FP32 planes, or the four 32 KiB bf16 planes, and the 32 KiB
+             // tile fill the 160 KiB of LDS; REGS takes the automatic choice (LDS)
+      if (o != SV_MFMA_OPERAND_GLOBAL)
+        return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3, OP_LDS>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32, OP_LDS>(tp, psi, op, st);
       return bf ? tile_mfma_k<7, 5, SV_PREC_BF16X3, OP_GLOBAL>(tp, psi, op, st) : tile_mfma_k<7, 5, SV_PREC_FP32, OP_GLOBAL>(tp, psi, op, st);
     default: return hipErrorInvalidValue;
   }
