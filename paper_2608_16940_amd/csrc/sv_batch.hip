@@ -37,10 +37,10 @@ struct BItem {
   int64_t state_off[kMaxPack];  // in amplitudes
 };
 
-__device__ __forceinline__ int64_t ins0(int64_t x, int p) {
-  const int64_t low = x & ((int64_t(1) << p) - 1);
-  return ((x >> p) << (p + 1)) | low;
-}
+
+// x with a zero bit inserted at position p (LDS indices: states and slices of
+// at most 2^14 amplitudes)
+__device__ __forceinline__ int ins0(int x, int p) { return ((x >> p) << (p + 1)) | (x & ((1 << p) - 1)); }
 
 __device__ __forceinline__ float2 cmad(float ar, float ai, float2 x, float2 acc) {
   acc.x = fmaf(ar, x.x, acc.x);
@@ -53,31 +53,29 @@ __device__ __forceinline__ float2 cmad(float ar, float ai, float2 x, float2 acc)
 constexpr int kSliceBits = 14;
 constexpr int kGatePass = SV_BATCH_PASS;  // record: q0 = slice qubit mask, q1 = gates in the pass
 
-// One gate on a state of `dim` amplitudes at st (LDS or global), threads lt of Tc.
-__device__ __forceinline__ void apply_gate(const BGate &G, float2 *st, int64_t dim, int lt, int Tc) {
-  if (G.kind == SV_BATCH_GATE_1Q) {
-    const int q = G.q0;
-    for (int64_t p = lt; p < dim / 2; p += Tc) {
-      const int64_t x = ins0(p, q), y = x | (int64_t(1) << q);
-      const float2 a = st[x], b = st[y];
-      float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
-      o0 = cmad(G.m[0], G.m[1], a, o0);
-      o0 = cmad(G.m[2], G.m[3], b, o0);
-      o1 = cmad(G.m[4], G.m[5], a, o1);
-      o1 = cmad(G.m[6], G.m[7], b, o1);
-      st[x] = o0;
-      st[y] = o1;
-    }
-  } else if (G.kind == SV_BATCH_GATE_CNOT) {
-    const int cq = G.q0, tq = G.q1;
-    const int lo = cq < tq ? cq : tq, hi = cq < tq ? tq : cq;
-    for (int64_t p = lt; p < dim / 4; p += Tc) {
-      const int64_t x = ins0(ins0(p, lo), hi) | (int64_t(1) << cq);
-      const int64_t y = x | (int64_t(1) << tq);
-      const float2 a = st[x];
-      st[x] = st[y];
-      st[y] = a;
-    }
+// LDS bank spreading.  When a gate's lowest qubit is low, the groups of
+// neighbouring lanes start 2^q amplitudes apart and a wave's accesses pile
+// onto a few banks (up to 32 lanes per 8-byte slot for qubits 0..3).  Each
+// lane therefore walks its group in an XOR-rotated order: element t of the
+// lane's registers holds amplitude t ^ r, with r taken from the group index
+// bits just above the lowest qubit, which puts neighbouring lanes on
+// different slots.  The rotation is exact: where r has bit j set, the pair
+// of qubit j arrives swapped, and the lane applies the 2x2 factor with rows
+// and columns swapped.  A CNOT's swap is symmetric and only its access order
+// changes.
+__device__ __forceinline__ int rot_shift(int lowest_qubit) { return lowest_qubit < 6 ? lowest_qubit : 6; }
+
+// One CNOT on a state of `dim` amplitudes at st (LDS or global), threads lt of Tc.
+__device__ __forceinline__ void apply_cnot(const BGate &G, float2 *st, int dim, int lt, int Tc) {
+  const int cq = G.q0, tq = G.q1;
+  const int lo = cq < tq ? cq : tq, hi = cq < tq ? tq : cq;
+  const int s = rot_shift(lo);
+  for (int p = lt; p < dim / 4; p += Tc) {
+    const int x = ins0(ins0(p, lo), hi) | (1 << cq);
+    const int x0 = x | (((p >> s) & 1) << tq), x1 = x0 ^ (1 << tq);
+    const float2 a = st[x0], b = st[x1];
+    st[x0] = b;
+    st[x1] = a;
   }
 }
 
@@ -87,10 +85,14 @@ __device__ __forceinline__ void apply_gate(const BGate &G, float2 *st, int64_t d
 // registers and applies every 2x2 factor there (one LDS read and write per
 // amplitude instead of c).
 template <int C>
-__device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int64_t dim, int lt, int Tc) {
+__device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int dim, int lt, int Tc) {
   int qs[C], srt[C];
+  int qbit[C];
 #pragma unroll
-  for (int j = 0; j < C; ++j) qs[j] = srt[j] = M[j].q0;
+  for (int j = 0; j < C; ++j) {
+    qs[j] = srt[j] = M[j].q0;
+    qbit[j] = 1 << qs[j];
+  }
 #pragma unroll
   for (int i = 1; i < C; ++i)
 #pragma unroll
@@ -100,42 +102,51 @@ __device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int64_
         srt[j] = srt[j - 1];
         srt[j - 1] = t;
       }
-  for (int64_t p = lt; p < (dim >> C); p += Tc) {
-    int64_t base = p;
+  const int s = rot_shift(srt[0]);
+  for (int p = lt; p < (dim >> C); p += Tc) {
+    int base = p;
 #pragma unroll
     for (int j = 0; j < C; ++j) base = ins0(base, srt[j]);
+    const int r = int(p >> s) & ((1 << C) - 1);  // element t holds amplitude t ^ r
+    int orot = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if ((r >> j) & 1) orot |= qbit[j];
     float2 a[1 << C];
 #pragma unroll
     for (int t = 0; t < (1 << C); ++t) {
-      int64_t o = 0;
+      int o = 0;
 #pragma unroll
       for (int j = 0; j < C; ++j)
-        if ((t >> j) & 1) o |= int64_t(1) << qs[j];
-      a[t] = st[base + o];
+        if ((t >> j) & 1) o |= qbit[j];
+      a[t] = st[base + (o ^ orot)];
     }
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const float *m = M[j].m;
+      const bool sw = (r >> j) & 1;  // this lane holds qubit j's pairs swapped
+      const float m0 = sw ? m[6] : m[0], m1 = sw ? m[7] : m[1], m2 = sw ? m[4] : m[2], m3 = sw ? m[5] : m[3];
+      const float m4 = sw ? m[2] : m[4], m5 = sw ? m[3] : m[5], m6 = sw ? m[0] : m[6], m7 = sw ? m[1] : m[7];
 #pragma unroll
       for (int t = 0; t < (1 << C); ++t) {
         if ((t >> j) & 1) continue;
         const float2 x = a[t], y = a[t | (1 << j)];
         float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
-        o0 = cmad(m[0], m[1], x, o0);
-        o0 = cmad(m[2], m[3], y, o0);
-        o1 = cmad(m[4], m[5], x, o1);
-        o1 = cmad(m[6], m[7], y, o1);
+        o0 = cmad(m0, m1, x, o0);
+        o0 = cmad(m2, m3, y, o0);
+        o1 = cmad(m4, m5, x, o1);
+        o1 = cmad(m6, m7, y, o1);
         a[t] = o0;
         a[t | (1 << j)] = o1;
       }
     }
 #pragma unroll
     for (int t = 0; t < (1 << C); ++t) {
-      int64_t o = 0;
+      int o = 0;
 #pragma unroll
       for (int j = 0; j < C; ++j)
-        if ((t >> j) & 1) o |= int64_t(1) << qs[j];
-      st[base + o] = a[t];
+        if ((t >> j) & 1) o |= qbit[j];
+      st[base + (o ^ orot)] = a[t];
     }
   }
 }
@@ -174,8 +185,9 @@ __device__ __forceinline__ void apply_linear(const BGate *R, float2 *lds, int ti
 static_assert(kLdsAmps == kBT << 5 && kSliceBits == 14, "linear records assume 2^14 slices over 512 threads");
 
 // One unit at record r (a gate, a group header and its members, or a linear
-// record and its mask record); returns the number of records it spans.
-__device__ __forceinline__ int apply_unit(const BGate *R, float2 *st, int64_t dim, int lt, int Tc) {
+// record and its mask record) on an LDS state or slice of dim <= 2^14
+// amplitudes; returns the number of records it spans.
+__device__ __forceinline__ int apply_unit(const BGate *R, float2 *st, int dim, int lt, int Tc) {
   if (R[0].kind == SV_BATCH_GATE_LINEAR) {
     apply_linear(R, st, lt);  // only in passes: dim = kLdsAmps, Tc = kBT
     return 2;
@@ -187,7 +199,10 @@ __device__ __forceinline__ int apply_unit(const BGate *R, float2 *st, int64_t di
     else apply_group_c<4>(R + 1, st, dim, lt, Tc);
     return 1 + c;
   }
-  apply_gate(R[0], st, dim, lt, Tc);
+  if (R[0].kind == SV_BATCH_GATE_1Q)
+    apply_group_c<1>(R, st, dim, lt, Tc);
+  else if (R[0].kind == SV_BATCH_GATE_CNOT)
+    apply_cnot(R[0], st, dim, lt, Tc);
   return 1;
 }
 
@@ -226,7 +241,7 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
       // past its last unit only meets the barriers
       int r = 0;  // this circuit's next record
       for (int g = 0; g < ngates; ++g) {
-        if (g < my_ng) r += apply_unit(gl + r, st, dim, lt, Tc);
+        if (g < my_ng) r += apply_unit(gl + r, st, int(dim), lt, Tc);
         __syncthreads();
       }
     } else {
