@@ -451,20 +451,24 @@ def bench_batch(args):
     updates = sum(len(g) * (1 << n) for n, g in circs)
     lds_peak = 256 * 128 * 2.4  # GB/s: 128 B per clock per CU at 2.4 GHz
 
-    # LDS bytes the kernel executes, from each circuit's records: 16 B per
-    # amplitude for a single-qubit gate, a group of them, a linear CNOT run
+    # Work the kernel executes, from each circuit's records.  LDS bytes: 16 B
+    # per amplitude for a single-qubit gate, a group of them, a linear CNOT run
     # and the copy of a pass's slices into and out of LDS; 8 B per amplitude
     # for a CNOT (half the amplitudes move); for a state held in LDS also the
-    # initial fill, the reduction of <Z_0> and the copy out (8 B each)
-    def lds_bytes(i):
+    # initial fill, the reduction of <Z_0> and the copy out (8 B each).  FP32
+    # flops: a 2x2 complex factor is 16 flops per amplitude (two complex
+    # multiply-adds), so a group of c factors is 16 c; CNOTs and linear runs
+    # only move data.
+    def executed_work(i):
         n = circs[i][0]
         recs, _ = b.records(i)
-        by = 0
+        by = fl = 0
         k = 0
         while k < len(recs):
             kind = int(recs[k][0])
             if kind == 3:  # group: the members ride in the same sweep
                 by += 16 << n
+                fl += 16 * int(recs[k][1]) << n
                 k += 1 + int(recs[k][1])
                 continue
             if kind == 4:  # linear CNOT run and its mask record
@@ -472,11 +476,16 @@ def bench_batch(args):
                 k += 2
                 continue
             by += (8 << n) if kind == 1 else (16 << n)  # CNOT, or single-qubit gate / pass copy
+            if kind == 0:
+                fl += 16 << n
             k += 1
         if n <= 14:
             by += 3 * (8 << n)
-        return by
-    executed = sum(lds_bytes(i) for i in range(len(circs)))
+        return by, fl
+    work = [executed_work(i) for i in range(len(circs))]
+    executed = sum(w[0] for w in work)
+    flops = sum(w[1] for w in work)
+    alu_peak = 157.3  # TFLOP/s FP32 vector (256 CUs x 2.4 GHz x 128 FMA lanes with packed FP32)
     # <Z_0> and sampled amplitudes against complex128 oracle values committed in
     # tests/golden (circuits 0, 64, ..., 4032 of the seed-0 family)
     z0 = b.launch()
@@ -528,11 +537,17 @@ def bench_batch(args):
                                % args.seed, "autotuned_pack_size": {str(n): int(cfg[n]) for n in range(10, 19)}},
         "seconds": t, "amplitude_updates_per_s": updates / t,
         "end_to_end_s_with_host_packing": t_e2e,
-        "roofline": {"bound": "lds", "kernel": "k_batch", "achieved": executed / t / 1e9, "peak": lds_peak,
-                     "unit": "GB/s", "frac": executed / t / 1e9 / lds_peak, "traffic": None,
-                     "lds_bytes_per_launch": executed,
-                     "note": "LDS bytes the records execute (gates, groups, linear CNOT runs, pass copies); "
-                             "per input gate, before fusion, the launch would move %.3g B" % (updates * 16)},
+        "roofline": {"bound": "alu", "kernel": "k_batch", "achieved": flops / t / 1e12, "peak": alu_peak,
+                     "unit": "TFLOP/s", "frac": flops / t / 1e12 / alu_peak, "traffic": None,
+                     "flops_per_launch": flops,
+                     "frac_of_unpacked_fp32": flops / t / 1e12 / (alu_peak / 2),
+                     "note": "FP32 flops of the 2x2 factors the records execute (16 per amplitude per factor); "
+                             "the kernels are built without packed FP32 instructions, so one FMA per lane per "
+                             "clock (78.6 TFLOP/s) is the rate this code can reach"},
+        "lds": {"achieved": executed / t / 1e9, "peak": lds_peak, "unit": "GB/s", "frac": executed / t / 1e9 / lds_peak,
+                "lds_bytes_per_launch": executed,
+                "note": "LDS bytes the records execute (gates, groups, linear CNOT runs, pass copies); "
+                        "per input gate, before fusion, the launch would move %.3g B" % (updates * 16)},
         "vs_oracle_golden_sample": sample,
         "one_launch_per_gate": {"circuits_per_s": per_gate_rate, "sample": "every 64th circuit (%d), gate by gate "
                                 "through sv_apply_fused" % len(sample_idx), "batched_speedup": (4096 / t) / per_gate_rate},
