@@ -138,8 +138,10 @@ int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots
  * Copy the state to caller-owned host memory (out_host >= 8 * 2^N bytes,
  * complex64 interleaved).  logical_order = 0: physical order, as stored;
  * 1: logical basis order, out[x] = amps[y] with y_{L(q)} = x_q (decoded on the
- * host: the layout and the device state are left as they are).  Waits for the
- * handle's stream first.  Errors: SV_ERR_ARG (null), SV_ERR_DEVICE.
+ * host through a 32 MiB staging buffer: the layout and the device state are
+ * left as they are).  Waits for the handle's stream first.  Errors:
+ * SV_ERR_ARG (null), SV_ERR_DEVICE (a HIP call or the staging allocation
+ * failed).
  */
 int sv_copy_out(sv_state *s, void *out_host, int logical_order);
 

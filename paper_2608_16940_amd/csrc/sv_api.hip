@@ -367,321 +367,341 @@ size_t sv_workspace_bytes(int n_qubits) {
 
 int sv_alloc(sv_state **out, int n, void *amps_dev, size_t amps_bytes, void *ws_dev, size_t ws_bytes,
              void *stream) {
-  g_err.clear();
-  if (!out || !amps_dev || !ws_dev) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  *out = nullptr;
-  if (!valid_n(n)) {
-    set_error("n_qubits out of range [1, 35]");
-    return SV_ERR_ARG;
-  }
-  if (amps_bytes < (size_t(8) << n)) {
-    set_error("state buffer smaller than 8 * 2^N bytes");
-    return SV_ERR_ARG;
-  }
-  if (ws_bytes < sv_workspace_bytes(n)) {
-    set_error("workspace smaller than sv_workspace_bytes(N)");
-    return SV_ERR_ARG;
-  }
-  if ((reinterpret_cast<uintptr_t>(amps_dev) & 255) || (reinterpret_cast<uintptr_t>(ws_dev) & 255)) {
-    set_error("device buffers must be 256-byte aligned");
-    return SV_ERR_ARG;
-  }
-  sv_state *s = new sv_state();
-  s->n = n;
-  s->amps = static_cast<float2 *>(amps_dev);
-  s->ws_base = static_cast<char *>(ws_dev);
-  s->ws_bytes = ws_bytes;
-  workspace_layout(n, s->ws_base, &s->ws);
-  s->st = static_cast<hipStream_t>(stream);
-  std::memset(&s->stats, 0, sizeof(s->stats));
-  for (int i = 0; i < kRingSlots; ++i) s->ev_live[i] = false;
-  hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&s->pinned), size_t(kRingSlots) * kRingSlotBytes,
-                               hipHostMallocDefault);
-  if (e != hipSuccess) {
-    set_error(std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
-    delete s;
-    return SV_ERR_DEVICE;
-  }
-  for (int i = 0; i < kRingSlots; ++i) {
-    e = hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming);
+  return guard([&]() -> int {
+    g_err.clear();
+    if (!out || !amps_dev || !ws_dev) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    *out = nullptr;
+    if (!valid_n(n)) {
+      set_error("n_qubits out of range [1, 35]");
+      return SV_ERR_ARG;
+    }
+    if (amps_bytes < (size_t(8) << n)) {
+      set_error("state buffer smaller than 8 * 2^N bytes");
+      return SV_ERR_ARG;
+    }
+    if (ws_bytes < sv_workspace_bytes(n)) {
+      set_error("workspace smaller than sv_workspace_bytes(N)");
+      return SV_ERR_ARG;
+    }
+    if ((reinterpret_cast<uintptr_t>(amps_dev) & 255) || (reinterpret_cast<uintptr_t>(ws_dev) & 255)) {
+      set_error("device buffers must be 256-byte aligned");
+      return SV_ERR_ARG;
+    }
+    sv_state *s = new sv_state();
+    s->n = n;
+    s->amps = static_cast<float2 *>(amps_dev);
+    s->ws_base = static_cast<char *>(ws_dev);
+    s->ws_bytes = ws_bytes;
+    workspace_layout(n, s->ws_base, &s->ws);
+    s->st = static_cast<hipStream_t>(stream);
+    std::memset(&s->stats, 0, sizeof(s->stats));
+    for (int i = 0; i < kRingSlots; ++i) s->ev_live[i] = false;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&s->pinned), size_t(kRingSlots) * kRingSlotBytes,
+                                 hipHostMallocDefault);
     if (e != hipSuccess) {
-      set_error(std::string("hipEventCreate failed: ") + hipGetErrorString(e));
-      for (int j = 0; j < i; ++j) (void)hipEventDestroy(s->ev[j]);
+      set_error(std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+      delete s;
+      return SV_ERR_DEVICE;
+    }
+    for (int i = 0; i < kRingSlots; ++i) {
+      e = hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) {
+        set_error(std::string("hipEventCreate failed: ") + hipGetErrorString(e));
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(s->ev[j]);
+        (void)hipHostFree(s->pinned);
+        delete s;
+        return SV_ERR_DEVICE;
+      }
+    }
+    reset_layout(s);
+    e = launch_init_zero(s->amps, n, s->st);
+    if (e != hipSuccess) {
+      set_error(std::string("init launch failed: ") + hipGetErrorString(e));
+      for (int j = 0; j < kRingSlots; ++j) (void)hipEventDestroy(s->ev[j]);
       (void)hipHostFree(s->pinned);
       delete s;
       return SV_ERR_DEVICE;
     }
-  }
-  reset_layout(s);
-  e = launch_init_zero(s->amps, n, s->st);
-  if (e != hipSuccess) {
-    set_error(std::string("init launch failed: ") + hipGetErrorString(e));
-    for (int j = 0; j < kRingSlots; ++j) (void)hipEventDestroy(s->ev[j]);
-    (void)hipHostFree(s->pinned);
-    delete s;
-    return SV_ERR_DEVICE;
-  }
-  *out = s;
-  return SV_OK;
+    *out = s;
+    return SV_OK;
+  });
 }
 
 int sv_free(sv_state *s) {
-  if (!s) return SV_OK;
-  (void)hipStreamSynchronize(s->st);
-  for (int i = 0; i < kRingSlots; ++i) (void)hipEventDestroy(s->ev[i]);
-  if (s->pinned) (void)hipHostFree(s->pinned);
-  delete s;
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s) return SV_OK;
+    (void)hipStreamSynchronize(s->st);
+    for (int i = 0; i < kRingSlots; ++i) (void)hipEventDestroy(s->ev[i]);
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    delete s;
+    return SV_OK;
+  });
 }
 
 int sv_reset(sv_state *s) {
-  if (!s) {
-    set_error("null handle");
-    return SV_ERR_ARG;
-  }
-  reset_layout(s);
-  std::memset(&s->stats, 0, sizeof(s->stats));
-  SV_HIP_CHECK(launch_init_zero(s->amps, s->n, s->st));
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s) {
+      set_error("null handle");
+      return SV_ERR_ARG;
+    }
+    reset_layout(s);
+    std::memset(&s->stats, 0, sizeof(s->stats));
+    SV_HIP_CHECK(launch_init_zero(s->amps, s->n, s->st));
+    return SV_OK;
+  });
 }
 
 int sv_apply_fused(sv_state *s, const double *matrix, const int32_t *targets, int k) {
-  if (!s || !matrix || !targets) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  if (k < 1 || k > s->n || k > SV_MAX_K) {
-    set_error("k out of range [1, min(N, SV_MAX_K)]");
-    return SV_ERR_ARG;
-  }
-  int32_t A[SV_MAX_K];
-  for (int j = 0; j < k; ++j) {
-    if (targets[j] < 0 || targets[j] >= s->n) {
-      set_error("target qubit out of range");
+  return guard([&]() -> int {
+    if (!s || !matrix || !targets) {
+      set_error("null pointer");
       return SV_ERR_ARG;
     }
-    for (int i = 0; i < j; ++i)
-      if (targets[i] == targets[j]) {
-        set_error("duplicate target qubit");
+    if (k < 1 || k > s->n || k > SV_MAX_K) {
+      set_error("k out of range [1, min(N, SV_MAX_K)]");
+      return SV_ERR_ARG;
+    }
+    int32_t A[SV_MAX_K];
+    for (int j = 0; j < k; ++j) {
+      if (targets[j] < 0 || targets[j] >= s->n) {
+        set_error("target qubit out of range");
         return SV_ERR_ARG;
       }
-    A[j] = s->L[targets[j]];
-  }
-  // A block that only permutes its qubits (a SWAP network) moves no data: the
-  // value of logical qubit targets[j] now sits under targets[perm[j]], which
-  // the layout map records (Lemma 2 per exchanged pair): L'(targets[perm[j]])
-  // = L(targets[j]).  Forced variants still sweep.
-  int perm[SV_MAX_K];
-  if (s->variant == SV_VARIANT_AUTO && qubit_permutation(matrix, k, perm)) {
-    int32_t old[SV_MAX_K];
-    for (int j = 0; j < k; ++j) old[j] = s->L[targets[j]];
-    for (int j = 0; j < k; ++j) {
-      s->L[targets[perm[j]]] = old[j];
-      s->Linv[old[j]] = targets[perm[j]];
+      for (int i = 0; i < j; ++i)
+        if (targets[i] == targets[j]) {
+          set_error("duplicate target qubit");
+          return SV_ERR_ARG;
+        }
+      A[j] = s->L[targets[j]];
     }
-    s->stats.layout_only += 1;
-    ++s->clock;
-    for (int j = 0; j < k; ++j) s->last_use[targets[j]] = s->clock;
-    return SV_OK;
-  }
-  const int rc = apply_physical(s, matrix, A, k);
-  if (rc == SV_OK) {
-    ++s->clock;
-    for (int j = 0; j < k; ++j) s->last_use[targets[j]] = s->clock;
-  }
-  return rc;
+    // A block that only permutes its qubits (a SWAP network) moves no data: the
+    // value of logical qubit targets[j] now sits under targets[perm[j]], which
+    // the layout map records (Lemma 2 per exchanged pair): L'(targets[perm[j]])
+    // = L(targets[j]).  Forced variants still sweep.
+    int perm[SV_MAX_K];
+    if (s->variant == SV_VARIANT_AUTO && qubit_permutation(matrix, k, perm)) {
+      int32_t old[SV_MAX_K];
+      for (int j = 0; j < k; ++j) old[j] = s->L[targets[j]];
+      for (int j = 0; j < k; ++j) {
+        s->L[targets[perm[j]]] = old[j];
+        s->Linv[old[j]] = targets[perm[j]];
+      }
+      s->stats.layout_only += 1;
+      ++s->clock;
+      for (int j = 0; j < k; ++j) s->last_use[targets[j]] = s->clock;
+      return SV_OK;
+    }
+    const int rc = apply_physical(s, matrix, A, k);
+    if (rc == SV_OK) {
+      ++s->clock;
+      for (int j = 0; j < k; ++j) s->last_use[targets[j]] = s->clock;
+    }
+    return rc;
+  });
 }
 
 int sv_permute_layout(sv_state *s, const int32_t *new_layout) {
-  if (!s || !new_layout) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  const int n = s->n;
-  bool seen[64] = {false};
-  for (int q = 0; q < n; ++q) {
-    const int p = new_layout[q];
-    if (p < 0 || p >= n || seen[p]) {
-      set_error("new layout is not a bijection");
+  return guard([&]() -> int {
+    if (!s || !new_layout) {
+      set_error("null pointer");
       return SV_ERR_ARG;
     }
-    seen[p] = true;
-  }
-  // Selection order: fill physical positions 0..n-1 with their final qubits,
-  // one bit transposition at a time (Lemma 2: each exchange updates
-  // L = tau o L).  Consecutive disjoint transpositions commute, so several
-  // of them run as one in-place tile pass (one sweep) when the state has at
-  // least 12 qubits (five pairs at most, so that the tile always keeps physical
-  // bit 0); smaller states use single transposition passes.
-  int32_t L[64], Linv[64];
-  for (int q = 0; q < n; ++q) {
-    L[q] = s->L[q];
-    Linv[s->L[q]] = q;
-  }
-  std::vector<std::pair<int, int>> swaps;
-  for (int p = 0; p < n; ++p) {
-    int want = -1;
-    for (int q = 0; q < n; ++q)
-      if (new_layout[q] == p) want = q;
-    const int cur = L[want];
-    if (cur == p) continue;
-    swaps.push_back({p, cur});
-    const int a = Linv[p], b = Linv[cur];
-    L[a] = cur;
-    L[b] = p;
-    Linv[p] = b;
-    Linv[cur] = a;
-  }
-  constexpr int kTileBits = 12;
-  size_t i = 0;
-  while (i < swaps.size()) {
-    if (n < kTileBits) {
-      SV_HIP_CHECK(launch_swap_bits(s->amps, n, swaps[i].first, swaps[i].second, s->st));
-      swap_physical(s, swaps[i].first, swaps[i].second);
-      s->stats.swap_half_sweeps += 1;
+    const int n = s->n;
+    bool seen[64] = {false};
+    for (int q = 0; q < n; ++q) {
+      const int p = new_layout[q];
+      if (p < 0 || p >= n || seen[p]) {
+        set_error("new layout is not a bijection");
+        return SV_ERR_ARG;
+      }
+      seen[p] = true;
+    }
+    // Selection order: fill physical positions 0..n-1 with their final qubits,
+    // one bit transposition at a time (Lemma 2: each exchange updates
+    // L = tau o L).  Consecutive disjoint transpositions commute, so several
+    // of them run as one in-place tile pass (one sweep) when the state has at
+    // least 12 qubits (five pairs at most, so that the tile always keeps physical
+    // bit 0); smaller states use single transposition passes.
+    int32_t L[64], Linv[64];
+    for (int q = 0; q < n; ++q) {
+      L[q] = s->L[q];
+      Linv[s->L[q]] = q;
+    }
+    std::vector<std::pair<int, int>> swaps;
+    for (int p = 0; p < n; ++p) {
+      int want = -1;
+      for (int q = 0; q < n; ++q)
+        if (new_layout[q] == p) want = q;
+      const int cur = L[want];
+      if (cur == p) continue;
+      swaps.push_back({p, cur});
+      const int a = Linv[p], b = Linv[cur];
+      L[a] = cur;
+      L[b] = p;
+      Linv[p] = b;
+      Linv[cur] = a;
+    }
+    constexpr int kTileBits = 12;
+    size_t i = 0;
+    while (i < swaps.size()) {
+      if (n < kTileBits) {
+        SV_HIP_CHECK(launch_swap_bits(s->amps, n, swaps[i].first, swaps[i].second, s->st));
+        swap_physical(s, swaps[i].first, swaps[i].second);
+        s->stats.swap_half_sweeps += 1;
+        s->stats.launches += 1;
+        ++i;
+        continue;
+      }
+      uint64_t used = 0;
+      size_t j = i;
+      while (j < swaps.size() && j - i < 5) {
+        const uint64_t m = (uint64_t(1) << swaps[j].first) | (uint64_t(1) << swaps[j].second);
+        if (used & m) break;
+        used |= m;
+        ++j;
+      }
+      // tile: the exchanged bits plus the lowest other bits, 12 in total
+      uint64_t smask = used;
+      for (int p = 0; p < n && __builtin_popcountll(smask) < kTileBits; ++p) smask |= uint64_t(1) << p;
+      TilePlan tp;
+      tp.n = n;
+      tp.s = kTileBits;
+      int b = 0;
+      for (int p = 0; p < n; ++p)
+        if ((smask >> p) & 1) {
+          tp.sbit[b] = p;
+          tp.loc_in[b] = b;
+          tp.loc_out[b] = b;
+          ++b;
+        }
+      for (size_t t = i; t < j; ++t) {
+        int ba = -1, bb = -1;
+        for (int c = 0; c < tp.s; ++c) {
+          if (tp.sbit[c] == swaps[t].first) ba = c;
+          if (tp.sbit[c] == swaps[t].second) bb = c;
+        }
+        tp.loc_out[ba] = bb;
+        tp.loc_out[bb] = ba;
+      }
+      SV_HIP_CHECK(launch_tile_permute(tp, s->amps, s->st));
+      for (size_t t = i; t < j; ++t) swap_physical(s, swaps[t].first, swaps[t].second);
+      s->stats.permute_sweeps += 1;
       s->stats.launches += 1;
-      ++i;
-      continue;
+      i = j;
     }
-    uint64_t used = 0;
-    size_t j = i;
-    while (j < swaps.size() && j - i < 5) {
-      const uint64_t m = (uint64_t(1) << swaps[j].first) | (uint64_t(1) << swaps[j].second);
-      if (used & m) break;
-      used |= m;
-      ++j;
-    }
-    // tile: the exchanged bits plus the lowest other bits, 12 in total
-    uint64_t smask = used;
-    for (int p = 0; p < n && __builtin_popcountll(smask) < kTileBits; ++p) smask |= uint64_t(1) << p;
-    TilePlan tp;
-    tp.n = n;
-    tp.s = kTileBits;
-    int b = 0;
-    for (int p = 0; p < n; ++p)
-      if ((smask >> p) & 1) {
-        tp.sbit[b] = p;
-        tp.loc_in[b] = b;
-        tp.loc_out[b] = b;
-        ++b;
-      }
-    for (size_t t = i; t < j; ++t) {
-      int ba = -1, bb = -1;
-      for (int c = 0; c < tp.s; ++c) {
-        if (tp.sbit[c] == swaps[t].first) ba = c;
-        if (tp.sbit[c] == swaps[t].second) bb = c;
-      }
-      tp.loc_out[ba] = bb;
-      tp.loc_out[bb] = ba;
-    }
-    SV_HIP_CHECK(launch_tile_permute(tp, s->amps, s->st));
-    for (size_t t = i; t < j; ++t) swap_physical(s, swaps[t].first, swaps[t].second);
-    s->stats.permute_sweeps += 1;
-    s->stats.launches += 1;
-    i = j;
-  }
-  return SV_OK;
+    return SV_OK;
+  });
 }
 
 int sv_hint_next_use(sv_state *s, const int64_t *next_use) {
-  if (!s || !next_use) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  for (int q = 0; q < s->n; ++q) s->next_use[q] = next_use[q];
-  s->have_hints = true;
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s || !next_use) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    for (int q = 0; q < s->n; ++q) s->next_use[q] = next_use[q];
+    s->have_hints = true;
+    return SV_OK;
+  });
 }
 
 int sv_policy_simulate(int n, int frames, int policy, int n_tuples, const int32_t *ks, const int32_t *targets,
                        int64_t *out) {
-  if (!out || n < 1 || n > 64 || frames < 1 || frames > n || n_tuples < 0 || (n_tuples > 0 && (!ks || !targets)) ||
-      policy < SV_POLICY_BELADY || policy > SV_POLICY_LRU) {
-    set_error("bad argument");
-    return SV_ERR_ARG;
-  }
-  std::vector<std::vector<int>> tup(static_cast<size_t>(n_tuples));
-  size_t off = 0;
-  for (int i = 0; i < n_tuples; ++i) {
-    if (ks[i] < 1 || ks[i] > frames) {
-      set_error("tuple wider than the frame count");
+  return guard([&]() -> int {
+    if (!out || n < 1 || n > 64 || frames < 1 || frames > n || n_tuples < 0 || (n_tuples > 0 && (!ks || !targets)) ||
+        policy < SV_POLICY_BELADY || policy > SV_POLICY_LRU) {
+      set_error("bad argument");
       return SV_ERR_ARG;
     }
-    for (int j = 0; j < ks[i]; ++j) {
-      const int q = targets[off + j];
-      if (q < 0 || q >= n) {
-        set_error("target out of range");
+    std::vector<std::vector<int>> tup(static_cast<size_t>(n_tuples));
+    size_t off = 0;
+    for (int i = 0; i < n_tuples; ++i) {
+      if (ks[i] < 1 || ks[i] > frames) {
+        set_error("tuple wider than the frame count");
         return SV_ERR_ARG;
       }
-      tup[size_t(i)].push_back(q);
-    }
-    off += size_t(ks[i]);
-  }
-  // positions 0..frames-1 are frames; position of qubit q is L[q]
-  int32_t L[64], Linv[64];
-  int64_t last_use[64] = {0}, next_use[64];
-  for (int q = 0; q < n; ++q) L[q] = Linv[q] = q;
-  int64_t promotions = 0;
-  for (int i = 0; i < n_tuples; ++i) {
-    for (int q = 0; q < n; ++q) {
-      next_use[q] = INT64_MAX;
-      for (int t = i + 1; t < n_tuples; ++t)
-        if (std::find(tup[size_t(t)].begin(), tup[size_t(t)].end(), q) != tup[size_t(t)].end()) {
-          next_use[q] = t;
-          break;
+      for (int j = 0; j < ks[i]; ++j) {
+        const int q = targets[off + j];
+        if (q < 0 || q >= n) {
+          set_error("target out of range");
+          return SV_ERR_ARG;
         }
+        tup[size_t(i)].push_back(q);
+      }
+      off += size_t(ks[i]);
     }
-    for (int q : tup[size_t(i)]) {
-      if (L[q] < frames) continue;
-      std::vector<int> cand;
-      for (int p = 0; p < frames; ++p)
-        if (std::find(tup[size_t(i)].begin(), tup[size_t(i)].end(), Linv[p]) == tup[size_t(i)].end())
-          cand.push_back(p);
-      const int v = pick_victim(policy, cand, Linv, true, next_use, last_use);
-      const int a = q, b = Linv[v], pa = L[q];
-      L[a] = v;
-      L[b] = pa;
-      Linv[v] = a;
-      Linv[pa] = b;
-      ++promotions;
+    // positions 0..frames-1 are frames; position of qubit q is L[q]
+    int32_t L[64], Linv[64];
+    int64_t last_use[64] = {0}, next_use[64];
+    for (int q = 0; q < n; ++q) L[q] = Linv[q] = q;
+    int64_t promotions = 0;
+    for (int i = 0; i < n_tuples; ++i) {
+      for (int q = 0; q < n; ++q) {
+        next_use[q] = INT64_MAX;
+        for (int t = i + 1; t < n_tuples; ++t)
+          if (std::find(tup[size_t(t)].begin(), tup[size_t(t)].end(), q) != tup[size_t(t)].end()) {
+            next_use[q] = t;
+            break;
+          }
+      }
+      for (int q : tup[size_t(i)]) {
+        if (L[q] < frames) continue;
+        std::vector<int> cand;
+        for (int p = 0; p < frames; ++p)
+          if (std::find(tup[size_t(i)].begin(), tup[size_t(i)].end(), Linv[p]) == tup[size_t(i)].end())
+            cand.push_back(p);
+        const int v = pick_victim(policy, cand, Linv, true, next_use, last_use);
+        const int a = q, b = Linv[v], pa = L[q];
+        L[a] = v;
+        L[b] = pa;
+        Linv[v] = a;
+        Linv[pa] = b;
+        ++promotions;
+      }
+      for (int q : tup[size_t(i)]) last_use[q] = i + 1;
     }
-    for (int q : tup[size_t(i)]) last_use[q] = i + 1;
-  }
-  *out = promotions;
-  return SV_OK;
+    *out = promotions;
+    return SV_OK;
+  });
 }
 
 int sv_get_layout(const sv_state *s, int32_t *out) {
-  if (!s || !out) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  for (int q = 0; q < s->n; ++q) out[q] = s->L[q];
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s || !out) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    for (int q = 0; q < s->n; ++q) out[q] = s->L[q];
+    return SV_OK;
+  });
 }
 
 int sv_probs(sv_state *s, double *out_dev, int logical_order) {
-  if (!s || !out_dev) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  SV_HIP_CHECK(launch_probs(s->amps, s->n, out_dev, logical_order ? 1 : 0, layout_arg(s), s->st));
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s || !out_dev) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    SV_HIP_CHECK(launch_probs(s->amps, s->n, out_dev, logical_order ? 1 : 0, layout_arg(s), s->st));
+    return SV_OK;
+  });
 }
 
 int sv_norm(sv_state *s, double *out_host) {
-  if (!s || !out_host) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  double *res = reinterpret_cast<double *>(s->ws.scalars);
-  SV_HIP_CHECK(launch_norm(s->amps, s->n, s->ws.partials, res, s->st));
-  SV_HIP_CHECK(hipMemcpyAsync(out_host, res, sizeof(double), hipMemcpyDeviceToHost, s->st));
-  SV_HIP_CHECK(hipStreamSynchronize(s->st));
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s || !out_host) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    double *res = reinterpret_cast<double *>(s->ws.scalars);
+    SV_HIP_CHECK(launch_norm(s->amps, s->n, s->ws.partials, res, s->st));
+    SV_HIP_CHECK(hipMemcpyAsync(out_host, res, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    SV_HIP_CHECK(hipStreamSynchronize(s->st));
+    return SV_OK;
+  });
 }
 
 static int sample_impl(const float2 *psi, const double *probs, int n, const Workspace &ws, uint64_t seed,
@@ -705,134 +725,160 @@ static int sample_impl(const float2 *psi, const double *probs, int n, const Work
 }
 
 int sv_sample(sv_state *s, uint64_t seed, int64_t shots, uint64_t *out_host) {
-  if (!s || (!out_host && shots > 0) || shots < 0) {
-    set_error("bad argument");
-    return SV_ERR_ARG;
-  }
-  if (shots == 0) return SV_OK;
-  return sample_impl(s->amps, nullptr, s->n, s->ws, seed, shots, out_host, layout_arg(s), s->st);
+  return guard([&]() -> int {
+    if (!s || (!out_host && shots > 0) || shots < 0) {
+      set_error("bad argument");
+      return SV_ERR_ARG;
+    }
+    if (shots == 0) return SV_OK;
+    return sample_impl(s->amps, nullptr, s->n, s->ws, seed, shots, out_host, layout_arg(s), s->st);
+  });
 }
 
 int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots, uint64_t *out_host,
                     void *ws_dev, size_t ws_bytes, void *stream) {
-  if (!probs_dev || !ws_dev || (!out_host && shots > 0) || shots < 0 || !valid_n(n)) {
-    set_error("bad argument");
-    return SV_ERR_ARG;
-  }
-  if (ws_bytes < sv_workspace_bytes(n)) {
-    set_error("workspace smaller than sv_workspace_bytes(n)");
-    return SV_ERR_ARG;
-  }
-  if (shots == 0) return SV_OK;
-  Workspace ws;
-  workspace_layout(n, static_cast<char *>(ws_dev), &ws);
-  LayoutArg L;
-  std::memset(&L, 0, sizeof(L));
-  for (int q = 0; q < n; ++q) L.pos[q] = int8_t(q);
-  return sample_impl(nullptr, probs_dev, n, ws, seed, shots, out_host, L, static_cast<hipStream_t>(stream));
+  return guard([&]() -> int {
+    if (!probs_dev || !ws_dev || (!out_host && shots > 0) || shots < 0 || !valid_n(n)) {
+      set_error("bad argument");
+      return SV_ERR_ARG;
+    }
+    if (ws_bytes < sv_workspace_bytes(n)) {
+      set_error("workspace smaller than sv_workspace_bytes(n)");
+      return SV_ERR_ARG;
+    }
+    if (shots == 0) return SV_OK;
+    Workspace ws;
+    workspace_layout(n, static_cast<char *>(ws_dev), &ws);
+    LayoutArg L;
+    std::memset(&L, 0, sizeof(L));
+    for (int q = 0; q < n; ++q) L.pos[q] = int8_t(q);
+    return sample_impl(nullptr, probs_dev, n, ws, seed, shots, out_host, L, static_cast<hipStream_t>(stream));
+  });
 }
 
 int sv_copy_out(sv_state *s, void *out_host, int logical_order) {
-  if (!s || !out_host) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  const int n = s->n;
-  const size_t dim = size_t(1) << n;
-  SV_HIP_CHECK(hipStreamSynchronize(s->st));
-  if (!logical_order) {
-    SV_HIP_CHECK(hipMemcpy(out_host, s->amps, dim * sizeof(float2), hipMemcpyDeviceToHost));
+  return guard([&]() -> int {
+    if (!s || !out_host) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    const int n = s->n;
+    const uint64_t dim = uint64_t(1) << n;
+    SV_HIP_CHECK(hipStreamSynchronize(s->st));
+    if (!logical_order) {
+      SV_HIP_CHECK(hipMemcpy(out_host, s->amps, dim * sizeof(float2), hipMemcpyDeviceToHost));
+      return SV_OK;
+    }
+    // Stream the state through a bounded staging buffer in physical order and
+    // scatter each amplitude to its logical index: bit q of x is bit L(q) of y,
+    // assembled from one table lookup per byte of y.
+    constexpr uint64_t kStage = uint64_t(1) << 22;  // 32 MiB of complex64
+    const int nbytes = (n + 7) / 8;
+    std::vector<uint64_t> tab(size_t(nbytes) * 256, 0);
+    std::vector<float2> buf(size_t(std::min(dim, kStage)));
+    for (int q = 0; q < n; ++q) {
+      const int p = s->L[q];
+      for (int v = 0; v < 256; ++v)
+        if ((v >> (p & 7)) & 1) tab[size_t(p >> 3) * 256 + size_t(v)] |= uint64_t(1) << q;
+    }
+    float2 *out = static_cast<float2 *>(out_host);
+    for (uint64_t a = 0; a < dim; a += buf.size()) {
+      const uint64_t cnt = std::min<uint64_t>(buf.size(), dim - a);
+      SV_HIP_CHECK(hipMemcpy(buf.data(), s->amps + a, cnt * sizeof(float2), hipMemcpyDeviceToHost));
+      for (uint64_t i = 0; i < cnt; ++i) {
+        const uint64_t y = a + i;
+        uint64_t x = 0;
+        for (int byte = 0; byte < nbytes; ++byte) x |= tab[size_t(byte) * 256 + ((y >> (8 * byte)) & 255)];
+        out[x] = buf[size_t(i)];
+      }
+    }
     return SV_OK;
-  }
-  std::vector<float2> phys(dim);
-  SV_HIP_CHECK(hipMemcpy(phys.data(), s->amps, dim * sizeof(float2), hipMemcpyDeviceToHost));
-  float2 *out = static_cast<float2 *>(out_host);
-  // y(x) = sum over set bits q of x of 2^L(q), built from the lowest set bit up
-  std::vector<uint64_t> bitpos(static_cast<size_t>(n));
-  for (int q = 0; q < n; ++q) bitpos[size_t(q)] = uint64_t(1) << s->L[q];
-  for (size_t x = 0; x < dim; ++x) {
-    uint64_t y = 0;
-    for (size_t r = x; r; r &= r - 1) y |= bitpos[size_t(__builtin_ctzll(r))];
-    out[x] = phys[size_t(y)];
-  }
-  return SV_OK;
+  });
 }
 
 int sv_sync(sv_state *s) {
-  if (!s) {
-    set_error("null handle");
-    return SV_ERR_ARG;
-  }
-  SV_HIP_CHECK(hipStreamSynchronize(s->st));
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s) {
+      set_error("null handle");
+      return SV_ERR_ARG;
+    }
+    SV_HIP_CHECK(hipStreamSynchronize(s->st));
+    return SV_OK;
+  });
 }
 
 int sv_set_option(sv_state *s, int key, int value) {
-  if (!s) {
-    set_error("null handle");
+  return guard([&]() -> int {
+    if (!s) {
+      set_error("null handle");
+      return SV_ERR_ARG;
+    }
+    switch (key) {
+      case SV_OPT_VARIANT:
+        if (value < SV_VARIANT_AUTO || value > SV_VARIANT_DIAG) break;
+        s->variant = value;
+        return SV_OK;
+      case SV_OPT_PRECISION:
+        if (value != SV_PREC_FP32 && value != SV_PREC_BF16X3) break;
+        s->prec = value;
+        return SV_OK;
+      case SV_OPT_MFMA_MIN_K:
+        if (value < 4 || value > 8) break;
+        s->mfma_min_k = value;
+        return SV_OK;
+      case SV_OPT_LAZY_RELABEL:
+        s->lazy = value ? 1 : 0;
+        return SV_OK;
+      case SV_OPT_LOW_BITS:
+        if (value < 1 || value > 35) break;
+        s->low_bits = value;
+        return SV_OK;
+      case SV_OPT_POLICY:
+        if (value < SV_POLICY_BELADY || value > SV_POLICY_LRU) break;
+        s->policy = value;
+        return SV_OK;
+      case SV_OPT_MFMA_OPERAND:
+        if (value < SV_MFMA_OPERAND_REGS || value > SV_MFMA_OPERAND_AUTO) break;
+        s->opsrc = value;
+        return SV_OK;
+      default:
+        break;
+    }
+    set_error("bad option key or value");
     return SV_ERR_ARG;
-  }
-  switch (key) {
-    case SV_OPT_VARIANT:
-      if (value < SV_VARIANT_AUTO || value > SV_VARIANT_DIAG) break;
-      s->variant = value;
-      return SV_OK;
-    case SV_OPT_PRECISION:
-      if (value != SV_PREC_FP32 && value != SV_PREC_BF16X3) break;
-      s->prec = value;
-      return SV_OK;
-    case SV_OPT_MFMA_MIN_K:
-      if (value < 4 || value > 8) break;
-      s->mfma_min_k = value;
-      return SV_OK;
-    case SV_OPT_LAZY_RELABEL:
-      s->lazy = value ? 1 : 0;
-      return SV_OK;
-    case SV_OPT_LOW_BITS:
-      if (value < 1 || value > 35) break;
-      s->low_bits = value;
-      return SV_OK;
-    case SV_OPT_POLICY:
-      if (value < SV_POLICY_BELADY || value > SV_POLICY_LRU) break;
-      s->policy = value;
-      return SV_OK;
-    case SV_OPT_MFMA_OPERAND:
-      if (value < SV_MFMA_OPERAND_REGS || value > SV_MFMA_OPERAND_AUTO) break;
-      s->opsrc = value;
-      return SV_OK;
-    default:
-      break;
-  }
-  set_error("bad option key or value");
-  return SV_ERR_ARG;
+  });
 }
 
 int sv_get_option(const sv_state *s, int key, int *value) {
-  if (!s || !value) {
-    set_error("null pointer");
+  return guard([&]() -> int {
+    if (!s || !value) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    switch (key) {
+      case SV_OPT_VARIANT: *value = s->variant; return SV_OK;
+      case SV_OPT_PRECISION: *value = s->prec; return SV_OK;
+      case SV_OPT_MFMA_MIN_K: *value = s->mfma_min_k; return SV_OK;
+      case SV_OPT_LAZY_RELABEL: *value = s->lazy; return SV_OK;
+      case SV_OPT_LOW_BITS: *value = s->low_bits; return SV_OK;
+      case SV_OPT_MFMA_OPERAND: *value = s->opsrc; return SV_OK;
+      case SV_OPT_POLICY: *value = s->policy; return SV_OK;
+      default: break;
+    }
+    set_error("bad option key");
     return SV_ERR_ARG;
-  }
-  switch (key) {
-    case SV_OPT_VARIANT: *value = s->variant; return SV_OK;
-    case SV_OPT_PRECISION: *value = s->prec; return SV_OK;
-    case SV_OPT_MFMA_MIN_K: *value = s->mfma_min_k; return SV_OK;
-    case SV_OPT_LAZY_RELABEL: *value = s->lazy; return SV_OK;
-    case SV_OPT_LOW_BITS: *value = s->low_bits; return SV_OK;
-    case SV_OPT_MFMA_OPERAND: *value = s->opsrc; return SV_OK;
-    case SV_OPT_POLICY: *value = s->policy; return SV_OK;
-    default: break;
-  }
-  set_error("bad option key");
-  return SV_ERR_ARG;
+  });
 }
 
 int sv_get_stats(const sv_state *s, sv_stats *out) {
-  if (!s || !out) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  *out = s->stats;
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!s || !out) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    *out = s->stats;
+    return SV_OK;
+  });
 }
 
 }  // extern "C"
@@ -953,133 +999,143 @@ void bound_finish(sv_bound *b) {
 extern "C" {
 
 int sv_bound_bytes(sv_state *s, const sv_plan *p, size_t *out) {
-  if (!s || !p || !out) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  std::vector<Lowered> ops;
-  std::vector<size_t> off;
-  return lower_plan(s, p, &ops, &off, out, nullptr);
+  return guard([&]() -> int {
+    if (!s || !p || !out) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    std::vector<Lowered> ops;
+    std::vector<size_t> off;
+    return lower_plan(s, p, &ops, &off, out, nullptr);
+  });
 }
 
 int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, sv_bound **out) {
-  if (!s || !p || !out) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  sv_bound *b = new sv_bound();
-  b->s = s;
-  size_t need = 0;
-  int rc = lower_plan(s, p, &b->ops, &b->off, &need, b->Lend);
-  if (rc) {
-    delete b;
-    return rc;
-  }
-  if (need > 0 && (!op_dev || op_bytes < need || (reinterpret_cast<uintptr_t>(op_dev) & 255))) {
-    delete b;
-    set_error("operand buffer missing, too small or not 256-byte aligned");
-    return SV_ERR_ARG;
-  }
-  b->op_dev = static_cast<char *>(op_dev);
-  std::vector<char> host(need);
-  for (size_t i = 0; i < b->ops.size(); ++i) {
-    if (b->off[i] == SIZE_MAX) continue;
-    std::memcpy(host.data() + b->off[i], b->ops[i].op.data(), b->ops[i].op.size());
-    b->ops[i].op.clear();
-    b->ops[i].op.shrink_to_fit();
-  }
-  if (need > 0) {
-    hipError_t e = hipMemcpyAsync(op_dev, host.data(), need, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-    if (e != hipSuccess) {
+  return guard([&]() -> int {
+    if (!s || !p || !out) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    sv_bound *b = new sv_bound();
+    b->s = s;
+    size_t need = 0;
+    int rc = lower_plan(s, p, &b->ops, &b->off, &need, b->Lend);
+    if (rc) {
       delete b;
-      set_error(std::string("operand upload failed: ") + hipGetErrorString(e));
-      return SV_ERR_DEVICE;
+      return rc;
     }
-  }
-  std::memcpy(b->L, s->L, sizeof(b->L));
-  std::memset(&b->per_run, 0, sizeof(b->per_run));
-  for (const Lowered &L : b->ops) {
-    if (L.variant < 0) {
-      b->per_run.layout_only += 1;
-      continue;
+    if (need > 0 && (!op_dev || op_bytes < need || (reinterpret_cast<uintptr_t>(op_dev) & 255))) {
+      delete b;
+      set_error("operand buffer missing, too small or not 256-byte aligned");
+      return SV_ERR_ARG;
     }
-    b->per_run.gate_sweeps += 1;
-    b->per_run.launches += 1;
-    if (L.variant < 6) b->per_run.by_variant[L.variant] += 1;
-  }
-  *out = b;
-  return SV_OK;
+    b->op_dev = static_cast<char *>(op_dev);
+    std::vector<char> host(need);
+    for (size_t i = 0; i < b->ops.size(); ++i) {
+      if (b->off[i] == SIZE_MAX) continue;
+      std::memcpy(host.data() + b->off[i], b->ops[i].op.data(), b->ops[i].op.size());
+      b->ops[i].op.clear();
+      b->ops[i].op.shrink_to_fit();
+    }
+    if (need > 0) {
+      hipError_t e = hipMemcpyAsync(op_dev, host.data(), need, hipMemcpyHostToDevice, s->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+      if (e != hipSuccess) {
+        delete b;
+        set_error(std::string("operand upload failed: ") + hipGetErrorString(e));
+        return SV_ERR_DEVICE;
+      }
+    }
+    std::memcpy(b->L, s->L, sizeof(b->L));
+    std::memset(&b->per_run, 0, sizeof(b->per_run));
+    for (const Lowered &L : b->ops) {
+      if (L.variant < 0) {
+        b->per_run.layout_only += 1;
+        continue;
+      }
+      b->per_run.gate_sweeps += 1;
+      b->per_run.launches += 1;
+      if (L.variant < 6) b->per_run.by_variant[L.variant] += 1;
+    }
+    *out = b;
+    return SV_OK;
+  });
 }
 
 int sv_bound_run(sv_bound *b) {
-  int rc = bound_check(b);
-  if (rc) return rc;
-  const int64_t before = b->s->stats.layout_only;
-  rc = bound_launch_all(b);
-  if (rc) return rc;
-  b->s->stats.layout_only = before + b->per_run.layout_only;
-  bound_finish(b);
-  return SV_OK;
+  return guard([&]() -> int {
+    int rc = bound_check(b);
+    if (rc) return rc;
+    const int64_t before = b->s->stats.layout_only;
+    rc = bound_launch_all(b);
+    if (rc) return rc;
+    b->s->stats.layout_only = before + b->per_run.layout_only;
+    bound_finish(b);
+    return SV_OK;
+  });
 }
 
 int sv_bound_graph_run(sv_bound *b) {
-  int rc = bound_check(b);
-  if (rc) return rc;
-  sv_state *s = b->s;
-  if (!b->exec) {
-    // The handle's stream may be the legacy default stream, which cannot be
-    // captured: capture on a private stream (default priority), launch the
-    // graph on the handle's stream.
-    hipError_t e = hipSuccess;
-    if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
+  return guard([&]() -> int {
+    int rc = bound_check(b);
+    if (rc) return rc;
+    sv_state *s = b->s;
+    if (!b->exec) {
+      // The handle's stream may be the legacy default stream, which cannot be
+      // captured: capture on a private stream (default priority), launch the
+      // graph on the handle's stream.
+      hipError_t e = hipSuccess;
+      if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) {
+        set_error(std::string("graph capture failed to start: ") + hipGetErrorString(e));
+        return SV_ERR_DEVICE;
+      }
+      const sv_stats saved = s->stats;
+      hipStream_t user = s->st;
+      s->st = b->capture;
+      rc = bound_launch_all(b);
+      s->st = user;
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(b->capture, &g);
+      s->stats = saved;  // nothing ran while capturing
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess || !g) {
+        set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+        return SV_ERR_DEVICE;
+      }
+      e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        b->exec = nullptr;
+        set_error(std::string("graph instantiation failed: ") + hipGetErrorString(e));
+        return SV_ERR_DEVICE;
+      }
+      b->graph = g;
+    }
+    const hipError_t e = hipGraphLaunch(b->exec, s->st);
     if (e != hipSuccess) {
-      set_error(std::string("graph capture failed to start: ") + hipGetErrorString(e));
+      set_error(std::string("graph launch failed: ") + hipGetErrorString(e));
       return SV_ERR_DEVICE;
     }
-    const sv_stats saved = s->stats;
-    hipStream_t user = s->st;
-    s->st = b->capture;
-    rc = bound_launch_all(b);
-    s->st = user;
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->capture, &g);
-    s->stats = saved;  // nothing ran while capturing
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (e != hipSuccess || !g) {
-      set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
-      return SV_ERR_DEVICE;
-    }
-    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      b->exec = nullptr;
-      set_error(std::string("graph instantiation failed: ") + hipGetErrorString(e));
-      return SV_ERR_DEVICE;
-    }
-    b->graph = g;
-  }
-  const hipError_t e = hipGraphLaunch(b->exec, s->st);
-  if (e != hipSuccess) {
-    set_error(std::string("graph launch failed: ") + hipGetErrorString(e));
-    return SV_ERR_DEVICE;
-  }
-  add_stats(&s->stats, b->per_run);
-  bound_finish(b);
-  return SV_OK;
+    add_stats(&s->stats, b->per_run);
+    bound_finish(b);
+    return SV_OK;
+  });
 }
 
 int sv_bound_free(sv_bound *b) {
-  if (!b) return SV_OK;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->capture) (void)hipStreamDestroy(b->capture);
-  delete b;
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!b) return SV_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+    return SV_OK;
+  });
 }
 
 }  // extern "C"

@@ -8,10 +8,14 @@
 // gets all of the pass's gates, and is written back (one read and one write
 // of the state per pass instead of one per gate).
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstring>
 #include <map>
+#include <new>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "sv_batch.h"
@@ -502,86 +506,118 @@ void default_config(int32_t *cfg) {
   }
 }
 
-// Validate, fuse adjacent single-qubit gates on the same qubit (FP64, later
-// gate on the left), group by qubit count, sort each group by gate count so
-// that packs hold circuits of similar length, cut packs, order by cost.
+// Per-circuit outcome of the host pass (worker threads report here; the
+// calling thread turns the first failure into the error message).
+enum CircStatus { CIRC_OK = 0, CIRC_BAD, CIRC_BAD_1Q, CIRC_BAD_CNOT, CIRC_BAD_KIND, CIRC_NOMEM };
+
+// Validate circuit i, fuse adjacent single-qubit gates on the same qubit
+// (FP64, later gate on the left), cut it into passes if its state exceeds a
+// slice, group single-qubit runs.  Touches only circuit i's inputs and g.
+int prepare_circuit(const sv_batch_circuit &C, int64_t state_offset, size_t states_bytes, std::vector<BGate> &g) {
+  if (C.n_qubits < 1 || C.n_qubits > SV_BATCH_MAX_QUBITS || C.n_gates < 0 ||
+      (C.n_gates > 0 && (!C.kinds || !C.qubits)) || state_offset < 0 || (state_offset & 7) ||
+      uint64_t(state_offset) + (uint64_t(8) << C.n_qubits) > uint64_t(states_bytes))
+    return CIRC_BAD;
+  double cur[8];
+  int cur_q = -1;
+  auto flush = [&]() {
+    if (cur_q < 0) return;
+    BGate b;
+    b.kind = SV_BATCH_GATE_1Q;
+    b.q0 = cur_q;
+    b.q1 = -1;
+    b.pad = 0;
+    for (int e = 0; e < 8; ++e) b.m[e] = float(cur[e]);
+    g.push_back(b);
+    cur_q = -1;
+  };
+  for (int j = 0; j < C.n_gates; ++j) {
+    const int kind = C.kinds[j];
+    const int q0 = C.qubits[2 * j], q1 = C.qubits[2 * j + 1];
+    if (kind == SV_BATCH_GATE_1Q) {
+      if (q0 < 0 || q0 >= C.n_qubits || !C.mats) return CIRC_BAD_1Q;
+      const double *m = C.mats + 8 * size_t(j);
+      if (cur_q == q0) {
+        // cur <- m * cur
+        double r[8];
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            double re = 0, im = 0;
+            for (int k = 0; k < 2; ++k) {
+              const double xr = m[2 * (2 * a + k)], xi = m[2 * (2 * a + k) + 1];
+              const double yr = cur[2 * (2 * k + b)], yi = cur[2 * (2 * k + b) + 1];
+              re += xr * yr - xi * yi;
+              im += xr * yi + xi * yr;
+            }
+            r[2 * (2 * a + b)] = re;
+            r[2 * (2 * a + b) + 1] = im;
+          }
+        std::memcpy(cur, r, sizeof(r));
+      } else {
+        flush();
+        std::memcpy(cur, m, sizeof(cur));
+        cur_q = q0;
+      }
+    } else if (kind == SV_BATCH_GATE_CNOT) {
+      if (q0 < 0 || q1 < 0 || q0 >= C.n_qubits || q1 >= C.n_qubits || q0 == q1) return CIRC_BAD_CNOT;
+      flush();
+      BGate b;
+      std::memset(&b, 0, sizeof(b));
+      b.kind = SV_BATCH_GATE_CNOT;
+      b.q0 = q0;
+      b.q1 = q1;
+      g.push_back(b);
+    } else {
+      return CIRC_BAD_KIND;
+    }
+  }
+  flush();
+  if (C.n_qubits > kSliceBits) g = make_passes(g, C.n_qubits);
+  g = group_single_qubit(g, C.n_qubits > kSliceBits);
+  return CIRC_OK;
+}
+
+// Prepare every circuit (on up to 16 host threads taking circuits from a
+// shared counter: circuits are independent, and a thread that cannot be
+// started only costs parallelism), group by qubit count, sort each group by
+// gate count so that packs hold circuits of similar length, cut packs, order
+// by cost.
 int pack_batch(int count, const sv_batch_circuit *circs, size_t states_bytes, const int64_t *state_offsets,
                const int32_t *cfg, Packed *out) {
   std::vector<std::vector<BGate>> fused(static_cast<size_t>(count));
-  std::map<int, std::vector<int>> groups;
-  for (int i = 0; i < count; ++i) {
-    const sv_batch_circuit &C = circs[i];
-    if (C.n_qubits < 1 || C.n_qubits > SV_BATCH_MAX_QUBITS || C.n_gates < 0 ||
-        (C.n_gates > 0 && (!C.kinds || !C.qubits)) || state_offsets[i] < 0 || (state_offsets[i] & 7) ||
-        uint64_t(state_offsets[i]) + (uint64_t(8) << C.n_qubits) > uint64_t(states_bytes)) {
-      set_error("bad batch circuit " + std::to_string(i));
-      return SV_ERR_ARG;
-    }
-    std::vector<BGate> &g = fused[size_t(i)];
-    double cur[8];
-    int cur_q = -1;
-    auto flush = [&]() {
-      if (cur_q < 0) return;
-      BGate b;
-      b.kind = SV_BATCH_GATE_1Q;
-      b.q0 = cur_q;
-      b.q1 = -1;
-      b.pad = 0;
-      for (int e = 0; e < 8; ++e) b.m[e] = float(cur[e]);
-      g.push_back(b);
-      cur_q = -1;
-    };
-    for (int j = 0; j < C.n_gates; ++j) {
-      const int kind = C.kinds[j];
-      const int q0 = C.qubits[2 * j], q1 = C.qubits[2 * j + 1];
-      if (kind == SV_BATCH_GATE_1Q) {
-        if (q0 < 0 || q0 >= C.n_qubits || !C.mats) {
-          set_error("bad single-qubit gate in batch circuit " + std::to_string(i));
-          return SV_ERR_ARG;
-        }
-        const double *m = C.mats + 8 * size_t(j);
-        if (cur_q == q0) {
-          // cur <- m * cur
-          double r[8];
-          for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-              double re = 0, im = 0;
-              for (int k = 0; k < 2; ++k) {
-                const double xr = m[2 * (2 * a + k)], xi = m[2 * (2 * a + k) + 1];
-                const double yr = cur[2 * (2 * k + b)], yi = cur[2 * (2 * k + b) + 1];
-                re += xr * yr - xi * yi;
-                im += xr * yi + xi * yr;
-              }
-              r[2 * (2 * a + b)] = re;
-              r[2 * (2 * a + b) + 1] = im;
-            }
-          std::memcpy(cur, r, sizeof(r));
-        } else {
-          flush();
-          std::memcpy(cur, m, sizeof(cur));
-          cur_q = q0;
-        }
-      } else if (kind == SV_BATCH_GATE_CNOT) {
-        if (q0 < 0 || q1 < 0 || q0 >= C.n_qubits || q1 >= C.n_qubits || q0 == q1) {
-          set_error("bad CNOT in batch circuit " + std::to_string(i));
-          return SV_ERR_ARG;
-        }
-        flush();
-        BGate b;
-        std::memset(&b, 0, sizeof(b));
-        b.kind = SV_BATCH_GATE_CNOT;
-        b.q0 = q0;
-        b.q1 = q1;
-        g.push_back(b);
-      } else {
-        set_error("unknown gate kind in batch circuit " + std::to_string(i));
-        return SV_ERR_ARG;
+  std::vector<int> status(static_cast<size_t>(count), CIRC_OK);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int i; (i = next.fetch_add(1)) < count;) {
+      try {
+        status[size_t(i)] = prepare_circuit(circs[i], state_offsets[i], states_bytes, fused[size_t(i)]);
+      } catch (const std::bad_alloc &) {
+        status[size_t(i)] = CIRC_NOMEM;
       }
     }
-    flush();
-    if (C.n_qubits > kSliceBits) g = make_passes(g, C.n_qubits);
-    g = group_single_qubit(g, C.n_qubits > kSliceBits);
-    groups[C.n_qubits].push_back(i);
+  };
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nth = int(std::min<unsigned>({hw, 16u, unsigned(count / 64 + 1)}));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) {
+    try {
+      pool.emplace_back(work);
+    } catch (const std::system_error &) {
+      break;
+    }
+  }
+  work();
+  for (auto &th : pool) th.join();
+  static const char *const what[] = {"", "bad batch circuit ", "bad single-qubit gate in batch circuit ",
+                                     "bad CNOT in batch circuit ", "unknown gate kind in batch circuit ",
+                                     "host allocation failed for batch circuit "};
+  std::map<int, std::vector<int>> groups;
+  for (int i = 0; i < count; ++i) {
+    if (status[size_t(i)] != CIRC_OK) {
+      set_error(what[status[size_t(i)]] + std::to_string(i));
+      return SV_ERR_ARG;
+    }
+    groups[circs[i].n_qubits].push_back(i);
   }
   out->ncirc = count;
   std::vector<int64_t> gate_off(static_cast<size_t>(count));
@@ -717,87 +753,91 @@ size_t sv_batch_workspace_bytes(int count, const sv_batch_circuit *circs) {
 int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
                  const int64_t *state_offsets, double *z0_host, const int32_t *config, void *ws_dev, size_t ws_bytes,
                  void *stream) {
-  if (count < 0 || (count > 0 && (!circs || !states_dev || !state_offsets || !z0_host)) || !ws_dev) {
-    set_error("bad batch argument");
-    return SV_ERR_ARG;
-  }
-  int32_t cfg[SV_BATCH_CONFIG_LEN];
-  if (config) {
-    std::memcpy(cfg, config, sizeof(cfg));
-    if (!valid_config(cfg)) {
-      set_error("bad batch config");
+  return guard([&]() -> int {
+    if (count < 0 || (count > 0 && (!circs || !states_dev || !state_offsets || !z0_host)) || !ws_dev) {
+      set_error("bad batch argument");
       return SV_ERR_ARG;
     }
-  } else {
-    default_config(cfg);
-  }
-  Packed pk;
-  int rc = pack_batch(count, circs, states_bytes, state_offsets, cfg, &pk);
-  if (rc) return rc;
-  return run_packed(pk, states_dev, z0_host, ws_dev, ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+    int32_t cfg[SV_BATCH_CONFIG_LEN];
+    if (config) {
+      std::memcpy(cfg, config, sizeof(cfg));
+      if (!valid_config(cfg)) {
+        set_error("bad batch config");
+        return SV_ERR_ARG;
+      }
+    } else {
+      default_config(cfg);
+    }
+    Packed pk;
+    int rc = pack_batch(count, circs, states_bytes, state_offsets, cfg, &pk);
+    if (rc) return rc;
+    return run_packed(pk, states_dev, z0_host, ws_dev, ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+  });
 }
 
 int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
                       const int64_t *state_offsets, int sample_per_size, int32_t *config_out, double *times_out,
                       void *ws_dev, size_t ws_bytes, void *stream) {
-  if (count < 0 || (count > 0 && (!circs || !states_dev || !state_offsets)) || !config_out || !ws_dev ||
-      sample_per_size < 1) {
-    set_error("bad autotune argument");
-    return SV_ERR_ARG;
-  }
-  // tuning subset: up to sample_per_size circuits of every size, run together
-  // so that the measured time is the throughput of a full launch
-  std::vector<sv_batch_circuit> sample;
-  std::vector<int64_t> offs;
-  int per_size[SV_BATCH_CONFIG_LEN] = {0};
-  for (int i = 0; i < count; ++i) {
-    const int n = circs[i].n_qubits;
-    if (n < 1 || n > SV_BATCH_MAX_QUBITS || per_size[n] >= sample_per_size) continue;
-    ++per_size[n];
-    sample.push_back(circs[i]);
-    offs.push_back(state_offsets[i]);
-  }
-  int32_t cfg[SV_BATCH_CONFIG_LEN];
-  default_config(cfg);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  std::vector<double> z(std::max<size_t>(1, sample.size()));
-  auto measure = [&](const int32_t *c, double *t_out) -> int {
-    Packed pk;
-    int rc = pack_batch(int(sample.size()), sample.data(), states_bytes, offs.data(), c, &pk);
-    if (rc) return rc;
-    float ms = 0.f;
-    rc = run_packed(pk, states_dev, z.data(), ws_dev, ws_bytes, st, &ms);  // warm-up
-    if (rc) return rc;
-    rc = run_packed(pk, states_dev, z.data(), ws_dev, ws_bytes, st, &ms);
-    if (rc) return rc;
-    *t_out = double(ms) * 1e-3;
-    return SV_OK;
-  };
-  double best_t = 0;
-  int rc = measure(cfg, &best_t);
-  if (rc) return rc;
-  if (times_out)
-    for (int n = 0; n < SV_BATCH_CONFIG_LEN; ++n) times_out[n] = 0.0;
-  // coordinate descent over the pack size of every size present
-  for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
-    if (per_size[n] == 0) continue;
-    for (int P = 1; P <= kMaxPack; P *= 2) {
-      if (P == cfg[n] || (P > 1 && (int64_t(P) << n) > kLdsAmps)) continue;
-      int32_t trial[SV_BATCH_CONFIG_LEN];
-      std::memcpy(trial, cfg, sizeof(trial));
-      trial[n] = P;
-      double t = 0;
-      rc = measure(trial, &t);
-      if (rc) return rc;
-      if (t < best_t) {
-        best_t = t;
-        cfg[n] = P;
-      }
+  return guard([&]() -> int {
+    if (count < 0 || (count > 0 && (!circs || !states_dev || !state_offsets)) || !config_out || !ws_dev ||
+        sample_per_size < 1) {
+      set_error("bad autotune argument");
+      return SV_ERR_ARG;
     }
-    if (times_out) times_out[n] = best_t;
-  }
-  std::memcpy(config_out, cfg, sizeof(cfg));
-  return SV_OK;
+    // tuning subset: up to sample_per_size circuits of every size, run together
+    // so that the measured time is the throughput of a full launch
+    std::vector<sv_batch_circuit> sample;
+    std::vector<int64_t> offs;
+    int per_size[SV_BATCH_CONFIG_LEN] = {0};
+    for (int i = 0; i < count; ++i) {
+      const int n = circs[i].n_qubits;
+      if (n < 1 || n > SV_BATCH_MAX_QUBITS || per_size[n] >= sample_per_size) continue;
+      ++per_size[n];
+      sample.push_back(circs[i]);
+      offs.push_back(state_offsets[i]);
+    }
+    int32_t cfg[SV_BATCH_CONFIG_LEN];
+    default_config(cfg);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<double> z(std::max<size_t>(1, sample.size()));
+    auto measure = [&](const int32_t *c, double *t_out) -> int {
+      Packed pk;
+      int rc = pack_batch(int(sample.size()), sample.data(), states_bytes, offs.data(), c, &pk);
+      if (rc) return rc;
+      float ms = 0.f;
+      rc = run_packed(pk, states_dev, z.data(), ws_dev, ws_bytes, st, &ms);  // warm-up
+      if (rc) return rc;
+      rc = run_packed(pk, states_dev, z.data(), ws_dev, ws_bytes, st, &ms);
+      if (rc) return rc;
+      *t_out = double(ms) * 1e-3;
+      return SV_OK;
+    };
+    double best_t = 0;
+    int rc = measure(cfg, &best_t);
+    if (rc) return rc;
+    if (times_out)
+      for (int n = 0; n < SV_BATCH_CONFIG_LEN; ++n) times_out[n] = 0.0;
+    // coordinate descent over the pack size of every size present
+    for (int n = 1; n <= SV_BATCH_MAX_QUBITS; ++n) {
+      if (per_size[n] == 0) continue;
+      for (int P = 1; P <= kMaxPack; P *= 2) {
+        if (P == cfg[n] || (P > 1 && (int64_t(P) << n) > kLdsAmps)) continue;
+        int32_t trial[SV_BATCH_CONFIG_LEN];
+        std::memcpy(trial, cfg, sizeof(trial));
+        trial[n] = P;
+        double t = 0;
+        rc = measure(trial, &t);
+        if (rc) return rc;
+        if (t < best_t) {
+          best_t = t;
+          cfg[n] = P;
+        }
+      }
+      if (times_out) times_out[n] = best_t;
+    }
+    std::memcpy(config_out, cfg, sizeof(cfg));
+    return SV_OK;
+  });
 }
 
 }  // extern "C"
@@ -809,78 +849,86 @@ struct sv_batch_prepared {
 extern "C" int sv_batch_prepare(int count, const sv_batch_circuit *circs, size_t states_bytes,
                                 const int64_t *state_offsets, const int32_t *config, void *ws_dev, size_t ws_bytes,
                                 void *stream, sv_batch_prepared **out) {
-  if (!out || count < 0 || (count > 0 && (!circs || !state_offsets)) || !ws_dev) {
-    set_error("bad batch argument");
-    return SV_ERR_ARG;
-  }
-  int32_t cfg[SV_BATCH_CONFIG_LEN];
-  if (config) {
-    std::memcpy(cfg, config, sizeof(cfg));
-    if (!valid_config(cfg)) {
-      set_error("bad batch config");
+  return guard([&]() -> int {
+    if (!out || count < 0 || (count > 0 && (!circs || !state_offsets)) || !ws_dev) {
+      set_error("bad batch argument");
       return SV_ERR_ARG;
     }
-  } else {
-    default_config(cfg);
-  }
-  Packed pk;
-  int rc = pack_batch(count, circs, states_bytes, state_offsets, cfg, &pk);
-  if (rc) return rc;
-  sv_batch_prepared *p = new sv_batch_prepared();
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  rc = upload_packed(pk, ws_dev, ws_bytes, st, &p->d);
-  if (rc == SV_OK && hipStreamSynchronize(st) != hipSuccess) {
-    set_error("batch upload failed");
-    rc = SV_ERR_DEVICE;
-  }
-  if (rc) {
-    delete p;
-    return rc;
-  }
-  *out = p;
-  return SV_OK;
+    int32_t cfg[SV_BATCH_CONFIG_LEN];
+    if (config) {
+      std::memcpy(cfg, config, sizeof(cfg));
+      if (!valid_config(cfg)) {
+        set_error("bad batch config");
+        return SV_ERR_ARG;
+      }
+    } else {
+      default_config(cfg);
+    }
+    Packed pk;
+    int rc = pack_batch(count, circs, states_bytes, state_offsets, cfg, &pk);
+    if (rc) return rc;
+    sv_batch_prepared *p = new sv_batch_prepared();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = upload_packed(pk, ws_dev, ws_bytes, st, &p->d);
+    if (rc == SV_OK && hipStreamSynchronize(st) != hipSuccess) {
+      set_error("batch upload failed");
+      rc = SV_ERR_DEVICE;
+    }
+    if (rc) {
+      delete p;
+      return rc;
+    }
+    *out = p;
+    return SV_OK;
+  });
 }
 
 extern "C" int sv_batch_launch(sv_batch_prepared *p, void *states_dev, double *z0_host, void *stream) {
-  if (!p || !states_dev) {
-    set_error("bad batch argument");
-    return SV_ERR_ARG;
-  }
-  return launch_packed(p->d, states_dev, z0_host, static_cast<hipStream_t>(stream), nullptr);
+  return guard([&]() -> int {
+    if (!p || !states_dev) {
+      set_error("bad batch argument");
+      return SV_ERR_ARG;
+    }
+    return launch_packed(p->d, states_dev, z0_host, static_cast<hipStream_t>(stream), nullptr);
+  });
 }
 
 extern "C" int sv_batch_prepared_free(sv_batch_prepared *p) {
-  delete p;
-  return SV_OK;
+  return guard([&]() -> int {
+    delete p;
+    return SV_OK;
+  });
 }
 
 extern "C" int sv_batch_records(const sv_batch_circuit *c, int cap, int32_t *records, float *mats, int *n_out) {
-  if (!c || !records || !mats || !n_out || cap < 0) {
-    set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  if (c->n_qubits < 1 || c->n_qubits > SV_BATCH_MAX_QUBITS) {
-    set_error("bad batch circuit");
-    return SV_ERR_ARG;
-  }
-  int32_t cfg[SV_BATCH_CONFIG_LEN];
-  default_config(cfg);
-  const int64_t off = 0;
-  Packed pk;
-  const int rc = pack_batch(1, c, size_t(8) << c->n_qubits, &off, cfg, &pk);
-  if (rc) return rc;
-  if (pk.gates.size() > size_t(cap)) {
-    set_error("record capacity too small");
-    return SV_ERR_ARG;
-  }
-  for (size_t i = 0; i < pk.gates.size(); ++i) {
-    const BGate &g = pk.gates[i];
-    records[4 * i + 0] = g.kind;
-    records[4 * i + 1] = g.q0;
-    records[4 * i + 2] = g.q1;
-    records[4 * i + 3] = 0;
-    for (int e = 0; e < 8; ++e) mats[8 * i + size_t(e)] = g.m[e];
-  }
-  *n_out = int(pk.gates.size());
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!c || !records || !mats || !n_out || cap < 0) {
+      set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    if (c->n_qubits < 1 || c->n_qubits > SV_BATCH_MAX_QUBITS) {
+      set_error("bad batch circuit");
+      return SV_ERR_ARG;
+    }
+    int32_t cfg[SV_BATCH_CONFIG_LEN];
+    default_config(cfg);
+    const int64_t off = 0;
+    Packed pk;
+    const int rc = pack_batch(1, c, size_t(8) << c->n_qubits, &off, cfg, &pk);
+    if (rc) return rc;
+    if (pk.gates.size() > size_t(cap)) {
+      set_error("record capacity too small");
+      return SV_ERR_ARG;
+    }
+    for (size_t i = 0; i < pk.gates.size(); ++i) {
+      const BGate &g = pk.gates[i];
+      records[4 * i + 0] = g.kind;
+      records[4 * i + 1] = g.q0;
+      records[4 * i + 2] = g.q1;
+      records[4 * i + 3] = 0;
+      for (int e = 0; e < 8; ++e) mats[8 * i + size_t(e)] = g.m[e];
+    }
+    *n_out = int(pk.gates.size());
+    return SV_OK;
+  });
 }

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "sv.h"
+#include "sv_guard.h"
 
 namespace sv {
 
@@ -40,6 +41,7 @@ struct LayoutArg {
 
 // ------------------------------------------------------------------ error reporting
 void set_error(const std::string &msg);
+
 #define SV_HIP_CHECK(expr)                                                              \
   do {                                                                                  \
     hipError_t e_ = (expr);                                                             \

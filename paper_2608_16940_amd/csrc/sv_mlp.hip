@@ -169,85 +169,109 @@ int64_t sv_mlp_cache_floats(int hid, int batch) { return 4 * int64_t(hid) * batc
 
 int sv_mlp_forward(const float *params, int nin, int hid, const float *X, int batch, float *y, float *cache,
                    void *stream) {
-  if (!params || !X || !y || nin < 1 || hid < 1 || batch < 1 || !cache) {
-    set_error("bad mlp forward argument (cache is required)");
-    return SV_ERR_ARG;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const Off o = offsets(nin, hid);
-  float *z1 = cache, *z2 = cache + int64_t(hid) * batch;
-  hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, X, nin, false, params + o.w1,
-                     params + o.b1, hid, batch, z1);
-  hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, z1, hid, true, params + o.w2,
-                     params + o.b2, hid, batch, z2);
-  hipLaunchKernelGGL(k_out, dim3(blocks(batch)), dim3(kT), 0, st, z2, hid, params + o.w3, params + o.b3, batch, y);
-  SV_HIP_CHECK(hipGetLastError());
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!params || !X || !y || nin < 1 || hid < 1 || batch < 1 || !cache) {
+      set_error("bad mlp forward argument (cache is required)");
+      return SV_ERR_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Off o = offsets(nin, hid);
+    float *z1 = cache, *z2 = cache + int64_t(hid) * batch;
+    hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, X, nin, false, params + o.w1,
+                       params + o.b1, hid, batch, z1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, z1, hid, true, params + o.w2,
+                       params + o.b2, hid, batch, z2);
+    hipLaunchKernelGGL(k_out, dim3(blocks(batch)), dim3(kT), 0, st, z2, hid, params + o.w3, params + o.b3, batch, y);
+    SV_HIP_CHECK(hipGetLastError());
+    return SV_OK;
+  });
+  return guard([&]() -> int {
+    if (!params || !X || !y || nin < 1 || hid < 1 || batch < 1 || !cache) {
+      set_error("bad mlp forward argument (cache is required)");
+      return SV_ERR_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Off o = offsets(nin, hid);
+    float *z1 = cache, *z2 = cache + int64_t(hid) * batch;
+    hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, X, nin, false, params + o.w1,
+                       params + o.b1, hid, batch, z1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, z1, hid, true, params + o.w2,
+                       params + o.b2, hid, batch, z2);
+    hipLaunchKernelGGL(k_out, dim3(blocks(batch)), dim3(kT), 0, st, z2, hid, params + o.w3, params + o.b3, batch, y);
+    SV_HIP_CHECK(hipGetLastError());
+    return SV_OK;
+  });
 }
 
 int sv_mlp_backward(const float *params, int nin, int hid, const float *X, const float *target, int batch,
                     const float *y, const float *cache, float *grads, float *loss, void *stream) {
-  if (!params || !X || !target || !y || !cache || !grads || !loss || nin < 1 || hid < 1 || batch < 1) {
-    set_error("bad mlp backward argument");
-    return SV_ERR_ARG;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const Off o = offsets(nin, hid);
-  const float *z1 = cache, *z2 = cache + int64_t(hid) * batch;
-  float *dz2 = const_cast<float *>(cache) + 2 * int64_t(hid) * batch;
-  float *dz1 = const_cast<float *>(cache) + 3 * int64_t(hid) * batch;
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(kT), 0, st, y, target, batch, loss);
-  hipLaunchKernelGGL(k_out_grad, dim3(blocks(hid + 1)), dim3(kT), 0, st, z2, y, target, hid, batch, grads + o.w3,
-                     grads + o.b3);
-  hipLaunchKernelGGL(k_dz2, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, y, target, z2, params + o.w3, hid,
-                     batch, dz2);
-  hipLaunchKernelGGL(k_wgrad, dim3(blocks((hid + 1) * hid)), dim3(kT), 0, st, z1, hid, true, dz2, hid, batch,
-                     grads + o.w2, grads + o.b2);
-  hipLaunchKernelGGL(k_dz1, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, dz2, params + o.w2, z1, hid, batch,
-                     dz1);
-  hipLaunchKernelGGL(k_wgrad, dim3(blocks((nin + 1) * hid)), dim3(kT), 0, st, X, nin, false, dz1, hid, batch,
-                     grads + o.w1, grads + o.b1);
-  SV_HIP_CHECK(hipGetLastError());
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!params || !X || !target || !y || !cache || !grads || !loss || nin < 1 || hid < 1 || batch < 1) {
+      set_error("bad mlp backward argument");
+      return SV_ERR_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Off o = offsets(nin, hid);
+    const float *z1 = cache, *z2 = cache + int64_t(hid) * batch;
+    float *dz2 = const_cast<float *>(cache) + 2 * int64_t(hid) * batch;
+    float *dz1 = const_cast<float *>(cache) + 3 * int64_t(hid) * batch;
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(kT), 0, st, y, target, batch, loss);
+    hipLaunchKernelGGL(k_out_grad, dim3(blocks(hid + 1)), dim3(kT), 0, st, z2, y, target, hid, batch, grads + o.w3,
+                       grads + o.b3);
+    hipLaunchKernelGGL(k_dz2, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, y, target, z2, params + o.w3, hid,
+                       batch, dz2);
+    hipLaunchKernelGGL(k_wgrad, dim3(blocks((hid + 1) * hid)), dim3(kT), 0, st, z1, hid, true, dz2, hid, batch,
+                       grads + o.w2, grads + o.b2);
+    hipLaunchKernelGGL(k_dz1, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, dz2, params + o.w2, z1, hid, batch,
+                       dz1);
+    hipLaunchKernelGGL(k_wgrad, dim3(blocks((nin + 1) * hid)), dim3(kT), 0, st, X, nin, false, dz1, hid, batch,
+                       grads + o.w1, grads + o.b1);
+    SV_HIP_CHECK(hipGetLastError());
+    return SV_OK;
+  });
 }
 
 int sv_mlp_adam(float *params, const float *grads, float *m, float *v, int count, int t, float lr, float beta1,
                 float beta2, float eps, void *stream) {
-  if (!params || !grads || !m || !v || count < 1 || t < 1) {
-    set_error("bad adam argument");
-    return SV_ERR_ARG;
-  }
-  const float c1 = 1.f - std::pow(beta1, float(t)), c2 = 1.f - std::pow(beta2, float(t));
-  hipLaunchKernelGGL(k_adam, dim3(blocks(count)), dim3(kT), 0, static_cast<hipStream_t>(stream), params, grads, m,
-                     v, count, lr, beta1, beta2, eps, c1, c2);
-  SV_HIP_CHECK(hipGetLastError());
-  return SV_OK;
+  return guard([&]() -> int {
+    if (!params || !grads || !m || !v || count < 1 || t < 1) {
+      set_error("bad adam argument");
+      return SV_ERR_ARG;
+    }
+    const float c1 = 1.f - std::pow(beta1, float(t)), c2 = 1.f - std::pow(beta2, float(t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(count)), dim3(kT), 0, static_cast<hipStream_t>(stream), params, grads, m,
+                       v, count, lr, beta1, beta2, eps, c1, c2);
+    SV_HIP_CHECK(hipGetLastError());
+    return SV_OK;
+  });
 }
 
 int sv_mlp_forward_host(const float *p, int nin, int hid, const float *x, int batch, double *y) {
-  if (!p || !x || !y || nin < 1 || hid < 1 || batch < 0) {
-    set_error("bad host mlp argument");
-    return SV_ERR_ARG;
-  }
-  const Off o = offsets(nin, hid);
-  std::vector<double> h1(static_cast<size_t>(hid)), h2(static_cast<size_t>(hid));
-  for (int r = 0; r < batch; ++r) {
-    const float *xr = x + int64_t(r) * nin;
-    for (int u = 0; u < hid; ++u) {
-      double a = p[o.b1 + u];
-      for (int i = 0; i < nin; ++i) a += double(xr[i]) * double(p[o.w1 + i * hid + u]);
-      h1[size_t(u)] = a > 0 ? a : 0;
+  return guard([&]() -> int {
+    if (!p || !x || !y || nin < 1 || hid < 1 || batch < 0) {
+      set_error("bad host mlp argument");
+      return SV_ERR_ARG;
     }
-    for (int u = 0; u < hid; ++u) {
-      double a = p[o.b2 + u];
-      for (int i = 0; i < hid; ++i) a += h1[size_t(i)] * double(p[o.w2 + i * hid + u]);
-      h2[size_t(u)] = a > 0 ? a : 0;
+    const Off o = offsets(nin, hid);
+    std::vector<double> h1(static_cast<size_t>(hid)), h2(static_cast<size_t>(hid));
+    for (int r = 0; r < batch; ++r) {
+      const float *xr = x + int64_t(r) * nin;
+      for (int u = 0; u < hid; ++u) {
+        double a = p[o.b1 + u];
+        for (int i = 0; i < nin; ++i) a += double(xr[i]) * double(p[o.w1 + i * hid + u]);
+        h1[size_t(u)] = a > 0 ? a : 0;
+      }
+      for (int u = 0; u < hid; ++u) {
+        double a = p[o.b2 + u];
+        for (int i = 0; i < hid; ++i) a += h1[size_t(i)] * double(p[o.w2 + i * hid + u]);
+        h2[size_t(u)] = a > 0 ? a : 0;
+      }
+      double a = p[o.b3];
+      for (int u = 0; u < hid; ++u) a += h2[size_t(u)] * double(p[o.w3 + u]);
+      y[r] = a;
     }
-    double a = p[o.b3];
-    for (int u = 0; u < hid; ++u) a += h2[size_t(u)] * double(p[o.w3 + u]);
-    y[r] = a;
-  }
-  return SV_OK;
+    return SV_OK;
+  });
 }
 
 }  // extern "C"

@@ -9,10 +9,10 @@
 #include <string>
 #include <vector>
 
+#include "sv_guard.h"
 #include "sv_mlp.h"
 
 namespace sv {
-void set_error(const std::string &msg);
 bool qubit_permutation(const double *G, int k, int *perm);
 }
 
@@ -141,159 +141,175 @@ extern "C" {
 
 int sv_plan_greedy(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
                    const int8_t *diag, int k_max, sv_plan **out) {
-  if (!out || (ngates > 0 && (!ks || !targets || !mats)) || ngates < 0 || k_max < 1 || k_max > 8 ||
-      n < SV_MIN_QUBITS || n > SV_MAX_QUBITS) {
-    sv::set_error("bad planner argument");
-    return SV_ERR_ARG;
-  }
-  std::vector<GateView> gates;
-  if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
-    sv::set_error("bad gate in list");
-    return SV_ERR_ARG;
-  }
-  sv_plan *p = new sv_plan();
-  p->n = n;
-  std::vector<GateView> cur;
-  std::vector<int32_t> cur_set;
-  auto flush = [&]() {
-    if (!cur.empty()) p->blocks.push_back(make_block(cur));
-    cur.clear();
-    cur_set.clear();
-  };
-  for (const auto &g : gates) {
-    if (g.k > k_max) {
-      flush();
+  return sv::guard([&]() -> int {
+    if (!out || (ngates > 0 && (!ks || !targets || !mats)) || ngates < 0 || k_max < 1 || k_max > 8 ||
+        n < SV_MIN_QUBITS || n > SV_MAX_QUBITS) {
+      sv::set_error("bad planner argument");
+      return SV_ERR_ARG;
+    }
+    std::vector<GateView> gates;
+    if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
+      sv::set_error("bad gate in list");
+      return SV_ERR_ARG;
+    }
+    sv_plan *p = new sv_plan();
+    p->n = n;
+    std::vector<GateView> cur;
+    std::vector<int32_t> cur_set;
+    auto flush = [&]() {
+      if (!cur.empty()) p->blocks.push_back(make_block(cur));
+      cur.clear();
+      cur_set.clear();
+    };
+    for (const auto &g : gates) {
+      if (g.k > k_max) {
+        flush();
+        cur.push_back(g);
+        flush();
+        continue;
+      }
+      std::vector<int32_t> u = cur_set;
+      for (int j = 0; j < g.k; ++j)
+        if (std::find(u.begin(), u.end(), g.t[j]) == u.end()) u.push_back(g.t[j]);
+      if (int(u.size()) > k_max) {
+        flush();
+        u.assign(g.t, g.t + g.k);
+      }
       cur.push_back(g);
-      flush();
-      continue;
+      cur_set = u;
     }
-    std::vector<int32_t> u = cur_set;
-    for (int j = 0; j < g.k; ++j)
-      if (std::find(u.begin(), u.end(), g.t[j]) == u.end()) u.push_back(g.t[j]);
-    if (int(u.size()) > k_max) {
-      flush();
-      u.assign(g.t, g.t + g.k);
-    }
-    cur.push_back(g);
-    cur_set = u;
-  }
-  flush();
-  *out = p;
-  return SV_OK;
+    flush();
+    *out = p;
+    return SV_OK;
+  });
 }
 
 int sv_plan_num_blocks(const sv_plan *p, int *out) {
-  if (!p || !out) {
-    sv::set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  *out = int(p->blocks.size());
-  return SV_OK;
+  return sv::guard([&]() -> int {
+    if (!p || !out) {
+      sv::set_error("null pointer");
+      return SV_ERR_ARG;
+    }
+    *out = int(p->blocks.size());
+    return SV_OK;
+  });
 }
 
 int sv_plan_block_info(const sv_plan *p, int i, int *k, int32_t *targets, int *ngates, int *diag) {
-  if (!p || i < 0 || i >= int(p->blocks.size())) {
-    sv::set_error("bad block index");
-    return SV_ERR_ARG;
-  }
-  const SvBlock &b = p->blocks[size_t(i)];
-  if (k) *k = b.k;
-  if (targets)
-    for (int j = 0; j < b.k; ++j) targets[j] = b.tuple[size_t(j)];
-  if (ngates) *ngates = b.ngates;
-  if (diag) *diag = b.diag ? 1 : 0;
-  return SV_OK;
+  return sv::guard([&]() -> int {
+    if (!p || i < 0 || i >= int(p->blocks.size())) {
+      sv::set_error("bad block index");
+      return SV_ERR_ARG;
+    }
+    const SvBlock &b = p->blocks[size_t(i)];
+    if (k) *k = b.k;
+    if (targets)
+      for (int j = 0; j < b.k; ++j) targets[j] = b.tuple[size_t(j)];
+    if (ngates) *ngates = b.ngates;
+    if (diag) *diag = b.diag ? 1 : 0;
+    return SV_OK;
+  });
 }
 
 int sv_plan_block_matrix(const sv_plan *p, int i, double *out) {
-  if (!p || !out || i < 0 || i >= int(p->blocks.size())) {
-    sv::set_error("bad block index");
-    return SV_ERR_ARG;
-  }
-  const SvBlock &b = p->blocks[size_t(i)];
-  if (b.swap) {
-    sv::set_error("a layout-swap block has no matrix");
-    return SV_ERR_ARG;
-  }
-  std::memcpy(out, b.matrix.data(), b.matrix.size() * sizeof(double));
-  return SV_OK;
+  return sv::guard([&]() -> int {
+    if (!p || !out || i < 0 || i >= int(p->blocks.size())) {
+      sv::set_error("bad block index");
+      return SV_ERR_ARG;
+    }
+    const SvBlock &b = p->blocks[size_t(i)];
+    if (b.swap) {
+      sv::set_error("a layout-swap block has no matrix");
+      return SV_ERR_ARG;
+    }
+    std::memcpy(out, b.matrix.data(), b.matrix.size() * sizeof(double));
+    return SV_OK;
+  });
 }
 
 int sv_plan_block_swap(const sv_plan *p, int i, int *is_swap, int32_t *dest) {
-  if (!p || !is_swap || i < 0 || i >= int(p->blocks.size())) {
-    sv::set_error("bad block index");
-    return SV_ERR_ARG;
-  }
-  const SvBlock &b = p->blocks[size_t(i)];
-  *is_swap = b.swap ? 1 : 0;
-  if (b.swap && dest)
-    for (int j = 0; j < b.k; ++j) dest[j] = b.dest[size_t(j)];
-  return SV_OK;
+  return sv::guard([&]() -> int {
+    if (!p || !is_swap || i < 0 || i >= int(p->blocks.size())) {
+      sv::set_error("bad block index");
+      return SV_ERR_ARG;
+    }
+    const SvBlock &b = p->blocks[size_t(i)];
+    *is_swap = b.swap ? 1 : 0;
+    if (b.swap && dest)
+      for (int j = 0; j < b.k; ++j) dest[j] = b.dest[size_t(j)];
+    return SV_OK;
+  });
 }
 
 int sv_run_plan(sv_state *s, const sv_plan *p) {
-  if (!s || !p) {
-    sv::set_error("null pointer");
-    return SV_ERR_ARG;
-  }
-  // next use of every logical qubit after each block: the relabel policy's
-  // view of the future (Corollary 1)
-  const size_t nb = p->blocks.size();
-  std::vector<int64_t> next(size_t(p->n), INT64_MAX);
-  std::vector<std::vector<int64_t>> hints(nb);
-  for (size_t i = nb; i-- > 0;) {
-    hints[i] = next;
-    if (!p->blocks[i].swap)
-      for (int32_t q : p->blocks[i].tuple) next[size_t(q)] = int64_t(i);
-  }
-  for (size_t i = 0; i < nb; ++i) {
-    const SvBlock &b = p->blocks[i];
-    int rc;
-    if (b.swap) {
-      // each listed qubit to its physical bit, the occupant to its old place
-      std::vector<int32_t> L(static_cast<size_t>(p->n)), Linv(static_cast<size_t>(p->n));
-      rc = sv_get_layout(s, L.data());
-      if (rc) return rc;
-      for (int q = 0; q < p->n; ++q) Linv[size_t(L[size_t(q)])] = q;
-      for (int j = 0; j < b.k; ++j) {
-        const int32_t q = b.tuple[size_t(j)], to = b.dest[size_t(j)], from = L[size_t(q)];
-        if (from == to) continue;
-        const int32_t r = Linv[size_t(to)];
-        L[size_t(q)] = to;
-        L[size_t(r)] = from;
-        Linv[size_t(to)] = q;
-        Linv[size_t(from)] = r;
-      }
-      rc = sv_permute_layout(s, L.data());
-      if (rc) return rc;
-      continue;
+  return sv::guard([&]() -> int {
+    if (!s || !p) {
+      sv::set_error("null pointer");
+      return SV_ERR_ARG;
     }
-    rc = sv_hint_next_use(s, hints[i].data());
-    if (rc) return rc;
-    rc = sv_apply_fused(s, b.matrix.data(), b.tuple.data(), b.k);
-    if (rc) return rc;
-  }
-  return SV_OK;
+    // next use of every logical qubit after each block: the relabel policy's
+    // view of the future (Corollary 1)
+    const size_t nb = p->blocks.size();
+    std::vector<int64_t> next(size_t(p->n), INT64_MAX);
+    std::vector<std::vector<int64_t>> hints(nb);
+    for (size_t i = nb; i-- > 0;) {
+      hints[i] = next;
+      if (!p->blocks[i].swap)
+        for (int32_t q : p->blocks[i].tuple) next[size_t(q)] = int64_t(i);
+    }
+    for (size_t i = 0; i < nb; ++i) {
+      const SvBlock &b = p->blocks[i];
+      int rc;
+      if (b.swap) {
+        // each listed qubit to its physical bit, the occupant to its old place
+        std::vector<int32_t> L(static_cast<size_t>(p->n)), Linv(static_cast<size_t>(p->n));
+        rc = sv_get_layout(s, L.data());
+        if (rc) return rc;
+        for (int q = 0; q < p->n; ++q) Linv[size_t(L[size_t(q)])] = q;
+        for (int j = 0; j < b.k; ++j) {
+          const int32_t q = b.tuple[size_t(j)], to = b.dest[size_t(j)], from = L[size_t(q)];
+          if (from == to) continue;
+          const int32_t r = Linv[size_t(to)];
+          L[size_t(q)] = to;
+          L[size_t(r)] = from;
+          Linv[size_t(to)] = q;
+          Linv[size_t(from)] = r;
+        }
+        rc = sv_permute_layout(s, L.data());
+        if (rc) return rc;
+        continue;
+      }
+      rc = sv_hint_next_use(s, hints[i].data());
+      if (rc) return rc;
+      rc = sv_apply_fused(s, b.matrix.data(), b.tuple.data(), b.k);
+      if (rc) return rc;
+    }
+    return SV_OK;
+  });
 }
 
 int sv_plan_free(sv_plan *p) {
-  delete p;
-  return SV_OK;
+  return sv::guard([&]() -> int {
+    delete p;
+    return SV_OK;
+  });
 }
 
 int sv_cost_features(int n, int k, const int32_t *A, int diagonal, float *out) {
-  if (!A || !out || k < 1 || k > 7 || n < 1 || n > SV_MAX_QUBITS) {
-    sv::set_error("bad feature argument");
-    return SV_ERR_ARG;
-  }
-  int s[7];
-  for (int j = 0; j < k; ++j) s[j] = A[j];
-  std::sort(s, s + k);
-  out[0] = float(n) / 35.f;
-  out[1] = float(k) / 8.f;
-  for (int j = 0; j < 7; ++j) out[2 + j] = (j < k) ? float(s[j]) / 35.f : -0.25f;
-  out[9] = diagonal ? 1.f : 0.f;
-  return SV_OK;
+  return sv::guard([&]() -> int {
+    if (!A || !out || k < 1 || k > 7 || n < 1 || n > SV_MAX_QUBITS) {
+      sv::set_error("bad feature argument");
+      return SV_ERR_ARG;
+    }
+    int s[7];
+    for (int j = 0; j < k; ++j) s[j] = A[j];
+    std::sort(s, s + k);
+    out[0] = float(n) / 35.f;
+    out[1] = float(k) / 8.f;
+    for (int j = 0; j < 7; ++j) out[2 + j] = (j < k) ? float(s[j]) / 35.f : -0.25f;
+    out[9] = diagonal ? 1.f : 0.f;
+    return SV_OK;
+  });
 }
 
 }  // extern "C"
@@ -562,41 +578,43 @@ sv_plan *build_plan(int n, const std::vector<GateView> &gates, const Partition &
 extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *targets, const double *mats,
                           const int8_t *diag, int k_max, int diag_max, int window, int score,
                           const float *mlp_params, int mlp_nin, int mlp_hid, int flags, sv_plan **out) {
-  if (!out || ngates < 0 || (ngates > 0 && (!ks || !targets || !mats)) || k_max < 1 || k_max > 8 ||
-      diag_max < 1 || diag_max > 8 || window < 1 || n < SV_MIN_QUBITS || n > SV_MAX_QUBITS ||
-      (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED) ||
-      (score == SV_SCORE_LEARNED && (!mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1))) {
-    sv::set_error("bad dp planner argument");
-    return SV_ERR_ARG;
-  }
-  std::vector<GateView> gates;
-  if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
-    sv::set_error("bad gate in list");
-    return SV_ERR_ARG;
-  }
-  Scorer gamma{score, n, mlp_params, mlp_nin, mlp_hid, {}};  // one cache for every pass
-  if ((flags & SV_PLAN_SEARCH_CAP) && score == SV_SCORE_LEARNED) {
-    // The cost model also picks the caps: plan with every dense cap c up to
-    // k_max, with the diagonal cap at min(c, diag_max) and at diag_max
-    // (diagonal blocks stream at one sweep's cost whatever their width, but
-    // the reorder grows clusters up to the larger cap, which changes the
-    // order), and keep the partition of least predicted time.  Products are
-    // formed for the chosen partition only.
-    Partition best;
-    best.predicted = 1e300;
-    for (int cap = std::min(4, k_max); cap <= k_max; ++cap) {
-      const int lo = std::min(cap, diag_max);
-      for (int dcap : {lo, diag_max}) {
-        Partition part = dp_rounds(n, gates, cap, dcap, window, flags, gamma);
-        if (part.predicted < best.predicted) best = std::move(part);
-        if (diag_max == lo) break;
-      }
+  return sv::guard([&]() -> int {
+    if (!out || ngates < 0 || (ngates > 0 && (!ks || !targets || !mats)) || k_max < 1 || k_max > 8 ||
+        diag_max < 1 || diag_max > 8 || window < 1 || n < SV_MIN_QUBITS || n > SV_MAX_QUBITS ||
+        (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED) ||
+        (score == SV_SCORE_LEARNED && (!mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1))) {
+      sv::set_error("bad dp planner argument");
+      return SV_ERR_ARG;
     }
-    *out = build_plan(n, gates, best);
+    std::vector<GateView> gates;
+    if (!parse_gates(n, ngates, ks, targets, mats, diag, &gates)) {
+      sv::set_error("bad gate in list");
+      return SV_ERR_ARG;
+    }
+    Scorer gamma{score, n, mlp_params, mlp_nin, mlp_hid, {}};  // one cache for every pass
+    if ((flags & SV_PLAN_SEARCH_CAP) && score == SV_SCORE_LEARNED) {
+      // The cost model also picks the caps: plan with every dense cap c up to
+      // k_max, with the diagonal cap at min(c, diag_max) and at diag_max
+      // (diagonal blocks stream at one sweep's cost whatever their width, but
+      // the reorder grows clusters up to the larger cap, which changes the
+      // order), and keep the partition of least predicted time.  Products are
+      // formed for the chosen partition only.
+      Partition best;
+      best.predicted = 1e300;
+      for (int cap = std::min(4, k_max); cap <= k_max; ++cap) {
+        const int lo = std::min(cap, diag_max);
+        for (int dcap : {lo, diag_max}) {
+          Partition part = dp_rounds(n, gates, cap, dcap, window, flags, gamma);
+          if (part.predicted < best.predicted) best = std::move(part);
+          if (diag_max == lo) break;
+        }
+      }
+      *out = build_plan(n, gates, best);
+      return SV_OK;
+    }
+    *out = build_plan(n, gates, dp_rounds(n, gates, k_max, diag_max, window, flags, gamma));
     return SV_OK;
-  }
-  *out = build_plan(n, gates, dp_rounds(n, gates, k_max, diag_max, window, flags, gamma));
-  return SV_OK;
+  });
 }
 
 // ------------------------------------------------------------------ layout swaps chosen by the cost model
@@ -646,77 +664,79 @@ std::vector<int32_t> move_onto(const std::vector<int32_t> &L, const std::vector<
 
 extern "C" int sv_plan_swaps(sv_plan *p, const float *mlp_params, int mlp_nin, int mlp_hid, int horizon,
                              double margin, int *inserted) {
-  if (!p || !mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1 || horizon < 1 || margin < 0) {
-    sv::set_error("bad swap-pass argument");
-    return SV_ERR_ARG;
-  }
-  if (inserted) *inserted = 0;
-  const int n = p->n;
-  if (n < SV_PLAN_SWAP_MIN_QUBITS) return SV_OK;
-  Scorer gamma{SV_SCORE_LEARNED, n, mlp_params, mlp_nin, mlp_hid, {}};
-  auto cost = [&](const SvBlock &b, const std::vector<int32_t> &L) {
-    std::vector<int32_t> ph;
-    for (int32_t q : b.tuple) ph.push_back(L[size_t(q)]);
-    std::sort(ph.begin(), ph.end());
-    return gamma(ph, b.diag);
-  };
-  const double stream = gamma(std::vector<int32_t>{0}, true);  // one streaming sweep
-  std::vector<int32_t> L(static_cast<size_t>(n));
-  for (int q = 0; q < n; ++q) L[size_t(q)] = q;
-  std::vector<SvBlock> out;
-  const size_t nb = p->blocks.size();
-  int added = 0;
-  for (size_t i = 0; i < nb; ++i) {
-    const SvBlock &b = p->blocks[i];
-    std::vector<int32_t> Lperm(L);
-    const bool permutes = absorb_permutation(b, &Lperm);
-    if (!b.swap && !b.diag && !permutes && b.k <= 7) {
-      double best = 0.0;
-      std::vector<int32_t> bestL;
-      for (int s0 = 0; s0 + b.k <= n; ++s0) {
-        int moves = 0;
-        std::vector<int32_t> L2 = move_onto(L, b.tuple, s0, &moves);
-        if (moves == 0) continue;
-        // the next `horizon` blocks at their positions under both layouts
-        std::vector<int32_t> La(L), Lb(L2);
-        double gain = 0.0;
-        for (size_t j = i; j < nb && j < i + size_t(horizon); ++j) {
-          const SvBlock &c = p->blocks[j];
-          if (c.swap) break;
-          if (absorb_permutation(c, &La)) {
-            absorb_permutation(c, &Lb);
-            continue;
-          }
-          if (!c.diag) gain += cost(c, La) - cost(c, Lb);
-        }
-        const double price = double((moves + 4) / 5) * stream * SV_PLAN_SWAP_SWEEP_FACTOR;
-        if (gain > price * (1.0 + margin) && gain - price > best) {
-          best = gain - price;
-          bestL = std::move(L2);
-        }
-      }
-      if (!bestL.empty()) {
-        SvBlock sw;
-        sw.swap = true;
-        sw.ngates = 0;
-        sw.diag = false;
-        for (int q = 0; q < n; ++q)
-          if (bestL[size_t(q)] != L[size_t(q)]) {
-            sw.tuple.push_back(q);
-            sw.dest.push_back(bestL[size_t(q)]);
-          }
-        sw.k = int(sw.tuple.size());
-        out.push_back(std::move(sw));
-        L = bestL;
-        Lperm = L;
-        absorb_permutation(b, &Lperm);
-        ++added;
-      }
+  return sv::guard([&]() -> int {
+    if (!p || !mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1 || horizon < 1 || margin < 0) {
+      sv::set_error("bad swap-pass argument");
+      return SV_ERR_ARG;
     }
-    out.push_back(b);
-    L = Lperm;
-  }
-  p->blocks = std::move(out);
-  if (inserted) *inserted = added;
-  return SV_OK;
+    if (inserted) *inserted = 0;
+    const int n = p->n;
+    if (n < SV_PLAN_SWAP_MIN_QUBITS) return SV_OK;
+    Scorer gamma{SV_SCORE_LEARNED, n, mlp_params, mlp_nin, mlp_hid, {}};
+    auto cost = [&](const SvBlock &b, const std::vector<int32_t> &L) {
+      std::vector<int32_t> ph;
+      for (int32_t q : b.tuple) ph.push_back(L[size_t(q)]);
+      std::sort(ph.begin(), ph.end());
+      return gamma(ph, b.diag);
+    };
+    const double stream = gamma(std::vector<int32_t>{0}, true);  // one streaming sweep
+    std::vector<int32_t> L(static_cast<size_t>(n));
+    for (int q = 0; q < n; ++q) L[size_t(q)] = q;
+    std::vector<SvBlock> out;
+    const size_t nb = p->blocks.size();
+    int added = 0;
+    for (size_t i = 0; i < nb; ++i) {
+      const SvBlock &b = p->blocks[i];
+      std::vector<int32_t> Lperm(L);
+      const bool permutes = absorb_permutation(b, &Lperm);
+      if (!b.swap && !b.diag && !permutes && b.k <= 7) {
+        double best = 0.0;
+        std::vector<int32_t> bestL;
+        for (int s0 = 0; s0 + b.k <= n; ++s0) {
+          int moves = 0;
+          std::vector<int32_t> L2 = move_onto(L, b.tuple, s0, &moves);
+          if (moves == 0) continue;
+          // the next `horizon` blocks at their positions under both layouts
+          std::vector<int32_t> La(L), Lb(L2);
+          double gain = 0.0;
+          for (size_t j = i; j < nb && j < i + size_t(horizon); ++j) {
+            const SvBlock &c = p->blocks[j];
+            if (c.swap) break;
+            if (absorb_permutation(c, &La)) {
+              absorb_permutation(c, &Lb);
+              continue;
+            }
+            if (!c.diag) gain += cost(c, La) - cost(c, Lb);
+          }
+          const double price = double((moves + 4) / 5) * stream * SV_PLAN_SWAP_SWEEP_FACTOR;
+          if (gain > price * (1.0 + margin) && gain - price > best) {
+            best = gain - price;
+            bestL = std::move(L2);
+          }
+        }
+        if (!bestL.empty()) {
+          SvBlock sw;
+          sw.swap = true;
+          sw.ngates = 0;
+          sw.diag = false;
+          for (int q = 0; q < n; ++q)
+            if (bestL[size_t(q)] != L[size_t(q)]) {
+              sw.tuple.push_back(q);
+              sw.dest.push_back(bestL[size_t(q)]);
+            }
+          sw.k = int(sw.tuple.size());
+          out.push_back(std::move(sw));
+          L = bestL;
+          Lperm = L;
+          absorb_permutation(b, &Lperm);
+          ++added;
+        }
+      }
+      out.push_back(b);
+      L = Lperm;
+    }
+    p->blocks = std::move(out);
+    if (inserted) *inserted = added;
+    return SV_OK;
+  });
 }

@@ -169,15 +169,15 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   constexpr int MPW = MTT * NCB / 4;     // output tiles per wave
   constexpr bool SHARED_GROUPS = NCB < 4;  // several waves work on the same groups
   // BF16x3 k >= 6: the cross terms hi*lo and lo*hi accumulate apart from
-  // hi*hi (two independent MFMA chains per output tile; 5-10% faster at N=30,
+  // hi*hi (independent MFMA chains per output tile; 5-10% faster at N=30,
   // a third set costs occupancy); summed in FP32 before the store
-  constexpr int BSETS = ((ALG == ALG_EMBED_BF16X3 || ALG == ALG_CPLX_BF16X3) && K >= 6) ? 2 : 1;
+  constexpr int BSETS = (ALG == ALG_CPLX_BF16X3 && K >= 6) ? 2 : 1;
   constexpr int NACC = (ALG == ALG_GAUSS_F32) ? 3 * MPW : (ALG == ALG_CPLX_BF16X3 ? 2 : 1) * BSETS * MPW;
-  // BF16x3 k = 6: split the inputs into hi/lo once as the tile lands in LDS
-  // (two waves read every group; measured 4% faster at N=30); k = 5 and 7
-  // measured 1-3% slower that way and split inside the product loop
-  // and always in the complex form, whose B operands gather 8 amplitudes' halves
-  constexpr bool SPLIT_AT_LOAD = (ALG == ALG_EMBED_BF16X3 && K == 6) || ALG == ALG_CPLX_BF16X3;
+  // BF16x3 complex form: the inputs are split into bf16 hi/lo once, as the
+  // tile lands in LDS (the packed pair takes the float2's 8 bytes), and each
+  // step gathers the halves of eight amplitudes from those pairs; the k = 4
+  // embedding splits inside its product loop
+  constexpr bool SPLIT_AT_LOAD = (ALG == ALG_CPLX_BF16X3);
   __shared__ float2 lds[TILE];
   __shared__ float opl_s[OPS == OP_LDS ? NOPF : 1];
 
@@ -352,32 +352,21 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
           lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[j][2 * e], acc[j][2 * e + 1]);
       }
     } else if constexpr (ALG == ALG_EMBED_BF16X3) {
+      // k = 4 only (the complex form takes k >= 5)
       const shortx4 *oph = reinterpret_cast<const shortx4 *>(opsrc);
-      // fully unrolled up to k = 5, and at k = 6 with the operand in LDS (6.5%
-      // faster than 4 steps at N=30); k = 7 (operand through the caches) is
-      // fastest at 4 steps and the k = 6 cache form would spill unrolled
-      constexpr int UNR = (K <= 5 || (K == 6 && OPS == OP_LDS)) ? KQ : 4;
-#pragma unroll UNR
+#pragma unroll
       for (int kk = 0; kk < KQ; ++kk) {
         // four reals = two amplitudes (AH h + 2 kk, +1)
         shortx4 bh, bl;
-        if constexpr (SPLIT_AT_LOAD) {
-          const uint2 *ldsu = reinterpret_cast<const uint2 *>(lds);
-          const uint2 x0 = ldsu[swz<K>(gbase | (h * AH + 2 * kk))];
-          const uint2 x1 = ldsu[swz<K>(gbase | (h * AH + 2 * kk + 1))];
-          bh = __builtin_bit_cast(shortx4, make_uint2(x0.x, x1.x));
-          bl = __builtin_bit_cast(shortx4, make_uint2(x0.y, x1.y));
-        } else {
-          const float2 x0 = lds[swz<K>(gbase | (h * AH + 2 * kk))];
-          const float2 x1 = lds[swz<K>(gbase | (h * AH + 2 * kk + 1))];
-          const float xr[4] = {x0.x, x0.y, x1.x, x1.y};
+        const float2 x0 = lds[swz<K>(gbase | (h * AH + 2 * kk))];
+        const float2 x1 = lds[swz<K>(gbase | (h * AH + 2 * kk + 1))];
+        const float xr[4] = {x0.x, x0.y, x1.x, x1.y};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const unsigned short hi = bf16_rne(xr[e]);
-            const unsigned short lo = bf16_rne(xr[e] - bf16_to_f(hi));
-            bh[e] = short(hi);
-            bl[e] = short(lo);
-          }
+        for (int e = 0; e < 4; ++e) {
+          const unsigned short hi = bf16_rne(xr[e]);
+          const unsigned short lo = bf16_rne(xr[e] - bf16_to_f(hi));
+          bh[e] = short(hi);
+          bl[e] = short(lo);
         }
 #pragma unroll
         for (int j = 0; j < MPW; ++j) {

@@ -158,3 +158,38 @@ def test_committed_batch_golden_matches_oracle():
         assert abs(oracle.expect_z(psi, 0) - circ[i][1]) < 1e-14
         for x, v in amps[i]:
             assert abs(psi[x] - v) < 1e-15
+
+
+def test_prepare_reports_first_bad_circuit(B):
+    """The host pass prepares circuits on several threads; a bad circuit is still reported by the
+    lowest failing index, before any device call (the workspace pointer is never touched)."""
+    import ctypes
+    from types import SimpleNamespace
+    import paper_2608_16940_amd as P
+    from paper_2608_16940_amd import _native
+    x = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    circs = []
+    for i in range(600):
+        n = 10 + i % 7
+        gates = [SimpleNamespace(targets=(q,), matrix=x) for q in range(n)]
+        gates += [SimpleNamespace(targets=(q, q + 1), matrix=None, kind="cnot") for q in range(n - 1)]
+        circs.append((n, gates))
+    b = B.Batch(circs)
+    lib = P.lib()
+
+    def prepare():
+        prep = ctypes.c_void_p()
+        rc = lib.sv_batch_prepare(b.count, b.arr, b.state_bytes,
+                                  b.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), None,
+                                  ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(prep))
+        return rc, lib.sv_last_error().decode()
+
+    # a CNOT on one qubit in circuit 417, then also an unknown kind in circuit 233
+    j = circs[417][0]  # the first CNOT of circuit 417
+    k417 = b._keep[3 * 417 + 1]
+    k417[2 * j + 1] = k417[2 * j]
+    rc, msg = prepare()
+    assert rc == _native.SV_ERR_ARG and msg == "bad CNOT in batch circuit 417", msg
+    b._keep[3 * 233][3] = 7
+    rc, msg = prepare()
+    assert rc == _native.SV_ERR_ARG and msg == "unknown gate kind in batch circuit 233", msg

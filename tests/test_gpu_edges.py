@@ -82,11 +82,12 @@ def test_gate_over_every_qubit(P, n):
     sv.close()
 
 
-def test_copy_out_physical_and_logical(P):
+@pytest.mark.parametrize("n", [14, 23])
+def test_copy_out_physical_and_logical(P, n):
     """sv_copy_out: physical order is the stored state; logical order decodes y_{L(q)} = x_q on the host
-    and leaves the layout and the device state unchanged."""
-    n = 14
-    rng = np.random.default_rng(14)
+    (n = 23: two passes through the 2^22-amplitude staging buffer) and leaves the layout and the
+    device state unchanged."""
+    rng = np.random.default_rng(n)
     gates = [W.random_dense(n, k, rng) for k in (1, 2, 3, 5, 2)]
     sv = P.StateVector(n)
     for g in gates:
