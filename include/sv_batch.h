@@ -54,22 +54,15 @@ size_t sv_batch_workspace_bytes(int count, const sv_batch_circuit *circs);
  * must lie inside the buffer; slices must not overlap).  z0_host:
  * receives <Z_0> = sum_x |psi_x|^2 (1 - 2 x_0) per circuit, accumulated in
  * FP64.  config: pack sizes (NULL = defaults).  Synchronises `stream`.
- * Errors: SV_ERR_ARG (bad circuit or config, workspace too small).
+ * The host pass over the circuits (validation, fusion of single-qubit runs,
+ * slice passes) runs on up to 16 threads of the calling process; the first
+ * bad circuit by index is the one reported.  Errors: SV_ERR_ARG (bad circuit
+ * or config, workspace too small), SV_ERR_DEVICE.
  */
 int sv_batch_run(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
                  const int64_t *state_offsets, double *z0_host, const int32_t *config, void *ws_dev, size_t ws_bytes,
                  void *stream);
 
-/*
- * Pick config[n] for every qubit count present in the batch: a tuning subset
- * of up to `sample_per_size` circuits of every size is run as one launch
- * (hipEvent timing after one warm-up), starting from the default pack sizes,
- * and each size's pack size is varied in turn over the powers of two that
- * fit in LDS, keeping a change when the whole launch gets faster
- * (coordinate descent).  Writes SV_BATCH_CONFIG_LEN entries to config_out
- * and, if times_out is not NULL, the subset's launch time in seconds after
- * each size was tuned.  Uses states_dev / ws_dev like sv_batch_run.
- */
 /*
  * The same launch split in two, so that repeated runs of one batch (new
  * states each time, same circuits) do no host work: sv_batch_prepare packs
@@ -117,6 +110,16 @@ int sv_batch_prepared_free(sv_batch_prepared *p);
 #define SV_BATCH_GATE_LINEAR 4
 int sv_batch_records(const sv_batch_circuit *c, int cap, int32_t *records, float *mats, int *n_out);
 
+/*
+ * Pick config[n] for every qubit count present in the batch: a tuning subset
+ * of up to `sample_per_size` circuits of every size is run as one launch
+ * (hipEvent timing after one warm-up), starting from the default pack sizes,
+ * and each size's pack size is varied in turn over the powers of two that
+ * fit in LDS, keeping a change when the whole launch gets faster
+ * (coordinate descent).  Writes SV_BATCH_CONFIG_LEN entries to config_out
+ * and, if times_out is not NULL, the subset's launch time in seconds after
+ * each size was tuned.  Uses states_dev / ws_dev like sv_batch_run.
+ */
 int sv_batch_autotune(int count, const sv_batch_circuit *circs, void *states_dev, size_t states_bytes,
                       const int64_t *state_offsets, int sample_per_size, int32_t *config_out, double *times_out,
                       void *ws_dev, size_t ws_bytes, void *stream);
