@@ -210,7 +210,12 @@ def main():
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in blocks]
           for _ in range(args.steps)]
 
-    def step(timed_index):
+    # control bits each block's diagonal sweep skips (from the handle's
+    # statistics, in an untimed step): a sweep with c of them moves 2^-c of
+    # the state, which is what its algorithmic bytes count
+    ctl_bits = [0] * len(blocks)
+
+    def step(timed_index, probe=False):
         sv.reset()
         for j, b in enumerate(blocks):
             if timed_index is not None:
@@ -218,12 +223,16 @@ def main():
                 e0.record(stream)
                 apply_block(sv, b)
                 e1.record(stream)
+            elif probe:
+                c0 = sv.stats()["diag_control_bits"]
+                apply_block(sv, b)
+                ctl_bits[j] = sv.stats()["diag_control_bits"] - c0
             else:
                 apply_block(sv, b)
         return sv.sample(0x5EED, args.shots)
 
-    for w in range(args.warmup):
-        step(None)
+    for w in range(max(1, args.warmup)):  # the first (or only, untimed) warm-up step also probes
+        step(None, probe=(w == 0))
         torch.cuda.synchronize()
         log("bench: warmup %d done" % w)
     torch.cuda.synchronize()
@@ -233,24 +242,28 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     per_class = {}
+    sweep_bytes = 16.0 * (1 << n)
+    block_bytes = [0.0 if c == "layout" else sweep_bytes * 0.5 ** ctl_bits[j] for j, c in enumerate(classes)]
     for s in range(args.steps):
         for j, c in enumerate(classes):
             if c == "layout":
                 continue
             e0, e1 = ev[s][j]
-            per_class.setdefault(c, []).append(e0.elapsed_time(e1) / 1e3)
+            per_class.setdefault(c, []).append((e0.elapsed_time(e1) / 1e3, block_bytes[j]))
     log("bench: timed %d steps in %.3f s" % (args.steps, el))
 
     ms_per_step = el / args.steps * 1e3
     st = sv.stats()  # counters of the last step (they restart at each reset)
     sweeps = int(st["gate_sweeps"])  # fused blocks that ran a kernel; pure qubit permutations need none
     value = sweeps * args.steps / el
-    sweep_bytes = 16.0 * (1 << n)
     kernels = {}
-    for c, ts in per_class.items():
-        avg = float(np.mean(ts))
-        kernels[c] = {"launches": len(ts), "avg_ms": avg * 1e3, "total_ms_per_step": float(np.sum(ts)) * 1e3 / args.steps,
-                      "GBps": sweep_bytes / avg / 1e9, "frac": sweep_bytes / avg / 1e9 / HBM_PEAK_GBS}
+    for c, tb in per_class.items():
+        ts = [t for t, _ in tb]
+        by = [b for _, b in tb]
+        gbps = float(np.sum(by)) / float(np.sum(ts)) / 1e9
+        kernels[c] = {"launches": len(ts), "avg_ms": float(np.mean(ts)) * 1e3,
+                      "total_ms_per_step": float(np.sum(ts)) * 1e3 / args.steps,
+                      "bytes_per_launch": float(np.mean(by)), "GBps": gbps, "frac": gbps / HBM_PEAK_GBS}
     dom = max(kernels, key=lambda c: kernels[c]["total_ms_per_step"])
     achieved = kernels[dom]["GBps"]
     traffic = pmc_traffic(dom)
@@ -322,7 +335,9 @@ def main():
             "blocks_by_k": {str(k): v for k, v in sorted(kcount.items())}, "planner": "greedy",
             "parallelism": "single GPU",
         },
-        "effective_gbps_per_step": value * sweep_bytes / 1e9,
+        "effective_gbps_per_step": sum(block_bytes) / (ms_per_step / 1e3) / 1e9,
+        "controlled_diagonal_sweeps": sum(1 for c in ctl_bits if c > 0),
+        "diag_control_bits_per_step": int(sum(ctl_bits)),
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
@@ -333,7 +348,7 @@ def main():
             "traffic": traffic,
             "launches": kernels[dom]["launches"],
             "avg_ms": kernels[dom]["avg_ms"],
-            "bytes_per_launch": sweep_bytes,
+            "bytes_per_launch": kernels[dom]["bytes_per_launch"],
         },
         "kernels": {c: dict(v, traffic=pmc_traffic(c)) for c, v in kernels.items()},
         "cpu_baseline": cpu,
@@ -777,19 +792,24 @@ def bench_density(args):
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in blocks]
           for _ in range(args.steps)]
 
-    def step(i):
+    ctl_bits = [0] * len(blocks)  # control bits each diagonal sweep skips (untimed probe step)
+
+    def step(i, probe=False):
         dm.reset()
         for j, b in enumerate(blocks):
             if i is None:
+                c0 = dm.stats()["diag_control_bits"] if probe else 0
                 apply_block(dm, b)
+                if probe:
+                    ctl_bits[j] = dm.stats()["diag_control_bits"] - c0
             else:
                 ev[i][j][0].record(stream)
                 apply_block(dm, b)
                 ev[i][j][1].record(stream)
         return dm.sample(0x5EED, args.shots)
 
-    for _ in range(args.warmup):
-        step(None)
+    for w in range(max(1, args.warmup)):
+        step(None, probe=(w == 0))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -804,13 +824,16 @@ def bench_density(args):
     for s in range(args.steps):
         for j, c in enumerate(classes):
             if c != "layout":
-                per_class.setdefault(c, []).append(ev[s][j][0].elapsed_time(ev[s][j][1]) / 1e3)
+                per_class.setdefault(c, []).append((ev[s][j][0].elapsed_time(ev[s][j][1]) / 1e3,
+                                                    sweep_bytes * 0.5 ** ctl_bits[j]))
     kernels = {}
-    for c, ts in per_class.items():
-        avg = float(np.mean(ts))
-        kernels[c] = {"launches": len(ts), "avg_ms": avg * 1e3,
+    for c, tb in per_class.items():
+        ts = [t for t, _ in tb]
+        gbps = float(sum(b for _, b in tb)) / float(np.sum(ts)) / 1e9
+        kernels[c] = {"launches": len(ts), "avg_ms": float(np.mean(ts)) * 1e3,
                       "total_ms_per_step": float(np.sum(ts)) * 1e3 / args.steps,
-                      "GBps": sweep_bytes / avg / 1e9, "frac": sweep_bytes / avg / 1e9 / HBM_PEAK_GBS}
+                      "bytes_per_launch": float(np.mean([b for _, b in tb])), "GBps": gbps,
+                      "frac": gbps / HBM_PEAK_GBS}
     dom = max(kernels, key=lambda c: kernels[c]["total_ms_per_step"])
     # the 6-target superoperator sweeps are FP32-MFMA work: 6 * 2^6 flops per amplitude (Gauss form)
     mfma = None
@@ -856,7 +879,7 @@ def bench_density(args):
                      {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GBps"], "peak": HBM_PEAK_GBS,
                       "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": None,
                       "launches": kernels[dom]["launches"], "avg_ms": kernels[dom]["avg_ms"],
-                      "bytes_per_launch": sweep_bytes}),
+                      "bytes_per_launch": kernels[dom]["bytes_per_launch"]}),
         "kernels": kernels, "other_plans": others, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

@@ -189,6 +189,10 @@ std::vector<std::pair<int, int>> plan_relabel(const sv_state *s, const int32_t *
   return pairs;
 }
 
+// Lowest physical position a diagonal's control may take: a skipped half
+// then comes in runs of 2^4 amplitudes (128 bytes, whole cache lines).
+constexpr int kDiagControlMinBit = 4;
+
 // A gate resolved to one kernel launch: the chosen lowering, its physical
 // targets, operands passed by value, and the host bytes of an operand that
 // has to sit in device memory (MFMA operand, generic matrix, wide diagonal).
@@ -196,6 +200,8 @@ struct Lowered {
   int variant = SV_VARIANT_AUTO;
   int k = 0;
   int32_t A[8] = {0};
+  int nctl = 0;                // diagonal: controls whose clear half the sweep skips
+  int32_t ctl[8] = {0};        //   and their physical positions
   float2 m[256];               // by value: VALU matrix, shuffle 2x2, diagonal table with k <= 4
   bool by_value = false;
   std::vector<char> op;        // device operand bytes (empty when by value)
@@ -246,6 +252,16 @@ int lower(const sv_state *s, const double *matrix, const int32_t *A, int k, bool
       std::vector<float2> d(static_cast<size_t>(D));
       for (int r = 0; r < D; ++r)
         d[r] = make_float2(float(matrix[2 * (r * D + r)]), float(matrix[2 * (r * D + r) + 1]));
+      // controls: targets at which every entry with that bit clear is exactly
+      // 1 (FP64), so those amplitudes stay as they are; only positions from
+      // kDiagControlMinBit up, where the skipped runs span whole cache lines
+      for (int j = 0; j < k; ++j) {
+        if (A[j] < kDiagControlMinBit) continue;
+        bool ctl = true;
+        for (int r = 0; r < D && ctl; ++r)
+          if (!((r >> j) & 1) && (matrix[2 * (r * D + r)] != 1.0 || matrix[2 * (r * D + r) + 1] != 0.0)) ctl = false;
+        if (ctl) L->ctl[L->nctl++] = A[j];
+      }
       if (k <= 4) {  // small tables ride in the kernel arguments
         L->by_value = true;
         for (int r = 0; r < D; ++r) L->m[r] = d[r];
@@ -315,8 +331,9 @@ int launch_lowered(sv_state *s, const Lowered &L, const void *op_dev) {
   hipError_t e = hipSuccess;
   switch (L.variant) {
     case SV_VARIANT_DIAG:
-      e = L.by_value ? launch_diag(s->amps, n, L.k, L.A, nullptr, L.m, s->st)
-                     : launch_diag(s->amps, n, L.k, L.A, static_cast<const float2 *>(op_dev), nullptr, s->st);
+      e = L.by_value ? launch_diag(s->amps, n, L.k, L.A, nullptr, L.m, L.nctl, L.ctl, s->st)
+                     : launch_diag(s->amps, n, L.k, L.A, static_cast<const float2 *>(op_dev), nullptr, L.nctl,
+                                   L.ctl, s->st);
       break;
     case SV_VARIANT_SHUFFLE: e = launch_1q_shuffle(s->amps, n, L.A[0], L.m, s->st); break;
     case SV_VARIANT_VALU: e = launch_dense_valu(s->amps, n, L.k, L.A, L.m, s->st); break;
@@ -333,6 +350,7 @@ int launch_lowered(sv_state *s, const Lowered &L, const void *op_dev) {
   s->stats.gate_sweeps += 1;
   s->stats.launches += 1;
   if (L.variant >= 0 && L.variant < 6) s->stats.by_variant[L.variant] += 1;
+  s->stats.diag_control_bits += L.nctl;
   return SV_OK;
 }
 
@@ -983,6 +1001,7 @@ void add_stats(sv_stats *a, const sv_stats &d) {
   a->launches += d.launches;
   a->layout_only += d.layout_only;
   for (int v = 0; v < 6; ++v) a->by_variant[v] += d.by_variant[v];
+  a->diag_control_bits += d.diag_control_bits;
 }
 
 // After a run: the handle's layout is the one the absorbed permutations leave.
@@ -1056,6 +1075,7 @@ int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, s
       b->per_run.gate_sweeps += 1;
       b->per_run.launches += 1;
       if (L.variant < 6) b->per_run.by_variant[L.variant] += 1;
+      b->per_run.diag_control_bits += L.nctl;
     }
     *out = b;
     return SV_OK;

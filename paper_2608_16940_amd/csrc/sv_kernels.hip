@@ -8,6 +8,7 @@
 //   - FP64 probabilities and norm,
 //   - the two-level integer CDF sampler.
 // Every index is 64-bit: the state reaches 2^35 amplitudes.
+#include <algorithm>
 #include <cstring>
 
 #include "sv_internal.h"
@@ -158,34 +159,54 @@ __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ ps
 // amplitudes that differ in physical bit 0), in the streaming order of
 // stream_chunk; the 2^k table sits in LDS.  One chunk per thread over a full
 // grid (four per thread on a capped, grid-strided launch was 10% slower).
+//
+// Controlled diagonals.  Where the table is exactly 1 whenever some target
+// bit is 0 (that target is a control), the amplitudes with the bit clear are
+// left as they are, so the sweep visits only the chunks with every listed
+// control bit set: work item w becomes a chunk index by inserting a 1 at each
+// control's chunk-bit position (lowest first).  With c controls the pass
+// reads and writes 2^-c of the state.
 constexpr int kDiagByValue = 16;  // tables up to k = 4 travel in the kernel arguments
 struct DiagArgs {
   int k;
   int tgt[8];  // physical position of block bit j
   int bit0;    // r-bit set by physical bit 0 (0 if bit 0 is not a target)
+  int nctl;    // controls whose clear half is skipped
+  int ctl[8];  // their chunk-bit positions (physical position - 1), ascending
   float2 small[kDiagByValue];  // the table when dtab is null
 };
 
+__device__ __forceinline__ int64_t insert_one_bit(int64_t x, int p) {
+  const int64_t low = x & ((int64_t(1) << p) - 1);
+  return ((x >> p) << (p + 1)) | (int64_t(1) << p) | low;
+}
+
+// nwork = chunks visited: 2^(N-1) >> nctl.
 template <int UNR>
-__global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, int64_t nchunks,
+__global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, int64_t nwork,
                                                    const float2 *__restrict__ dtab, DiagArgs a) {
   __shared__ float2 tab[256];
   for (int i = threadIdx.x; i < (1 << a.k); i += kThreads) tab[i] = dtab ? dtab[i] : a.small[i];
   __syncthreads();
   const int64_t step = int64_t(gridDim.x) * kThreads * UNR;
-  for (int64_t c0 = int64_t(blockIdx.x) * kThreads * UNR + threadIdx.x; c0 < nchunks; c0 += step) {
+  for (int64_t c0 = int64_t(blockIdx.x) * kThreads * UNR + threadIdx.x; c0 < nwork; c0 += step) {
     floatx4 v[UNR];
     int64_t cc[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int64_t lin = c0 + int64_t(u) * kThreads;
-      cc[u] = lin < nchunks ? stream_chunk(lin, nchunks) : nchunks;
-      if (cc[u] < nchunks) v[u] = __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(psi4 + cc[u]));
+      cc[u] = -1;
+      if (lin < nwork) {
+        int64_t c = stream_chunk(lin, nwork);
+        for (int i = 0; i < a.nctl; ++i) c = insert_one_bit(c, a.ctl[i]);
+        cc[u] = c;
+        v[u] = __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(psi4 + c));
+      }
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int64_t c = cc[u];
-      if (c >= nchunks) continue;
+      if (c < 0) continue;
       const int64_t y = c << 1;  // first amplitude of the chunk; physical bit 0 is clear
       int r = 0;
       for (int j = 0; j < a.k; ++j) r |= int((y >> a.tgt[j]) & 1) << j;
@@ -570,8 +591,9 @@ hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStre
 }
 
 hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2 *d_dev, const float2 *d_host,
-                       hipStream_t st) {
-  if (k < 1 || k > 8 || k > n || (!d_dev && (!d_host || k > 4))) return hipErrorInvalidValue;
+                       int nctl, const int32_t *ctl_phys, hipStream_t st) {
+  if (k < 1 || k > 8 || k > n || (!d_dev && (!d_host || k > 4)) || nctl < 0 || nctl > k || (nctl && !ctl_phys))
+    return hipErrorInvalidValue;
   DiagArgs a;
   std::memset(&a, 0, sizeof(a));
   a.k = k;
@@ -581,10 +603,19 @@ hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2
     a.tgt[j] = A[j];
     if (A[j] == 0) a.bit0 = 1 << j;
   }
+  // controls: distinct targets above physical bit 0, as ascending chunk-bit positions
+  a.nctl = nctl;
+  for (int i = 0; i < nctl; ++i) {
+    if (ctl_phys[i] < 1 || ctl_phys[i] >= n) return hipErrorInvalidValue;
+    a.ctl[i] = ctl_phys[i] - 1;
+  }
+  std::sort(a.ctl, a.ctl + nctl);
+  for (int i = 1; i < nctl; ++i)
+    if (a.ctl[i] == a.ctl[i - 1]) return hipErrorInvalidValue;
   constexpr int UNR = 1;
-  const int64_t nchunks = int64_t(1) << (n - 1);
-  hipLaunchKernelGGL(k_diag<UNR>, dim3(grid_for(nchunks, kThreads * UNR, kFullGrid)), dim3(kThreads), 0, st,
-                     reinterpret_cast<float4 *>(psi), nchunks, d_dev, a);
+  const int64_t nwork = (int64_t(1) << (n - 1)) >> nctl;
+  hipLaunchKernelGGL(k_diag<UNR>, dim3(grid_for(nwork, kThreads * UNR, kFullGrid)), dim3(kThreads), 0, st,
+                     reinterpret_cast<float4 *>(psi), nwork, d_dev, a);
   return hipGetLastError();
 }
 

@@ -8,9 +8,12 @@ and writes the per-launch HBM bytes of the chosen kernel as JSON and
 markdown.  The JSON carries the hash of the kernel source it was taken on;
 bench.py reports the figure only while that source is unchanged.
 
-usage: python -m paper_2608_16940_amd.pmc_summary FETCH_CSV WRITE_CSV KERNEL_SUBSTR STATE_BYTES OUT_STEM "COMMAND..." [SOURCE]
+usage: python -m paper_2608_16940_amd.pmc_summary FETCH_CSV WRITE_CSV KERNEL_SUBSTR STATE_BYTES OUT_STEM "COMMAND..." [SOURCE [ALG_BYTES]]
 
 SOURCE is the kernel's source file under paper_2608_16940_amd/csrc (default sv_tile.hip).
+ALG_BYTES is the algorithmic bytes per launch averaged over the counted
+launches (default 2 * STATE_BYTES, a full sweep; less when some launches
+touch part of the state, as controlled diagonal sweeps do).
 """
 from __future__ import annotations
 
@@ -41,6 +44,7 @@ def main(argv):
     fetch_csv, write_csv, ksub, state_bytes, stem, cmd = argv[1:7]
     src = argv[7] if len(argv) > 7 else "sv_tile.hip"
     state_bytes = float(state_bytes)
+    alg = float(argv[8]) if len(argv) > 8 else 2 * state_bytes
     fv, fcopy = per_launch(fetch_csv, ksub)
     wv, wcopy = per_launch(write_csv, ksub)
     fscale = state_bytes / fcopy
@@ -53,7 +57,7 @@ def main(argv):
         "kernel": ksub, "launches": len(fv), "source": src, "source_sha": sha,
         "fetch_bytes_per_launch": f, "write_bytes_per_launch": w, "bytes_per_launch": f + w,
         "fetch_scale_from_copy": fscale, "write_scale_from_copy": wscale,
-        "copy_probe_bytes_each_way": state_bytes, "command": cmd,
+        "copy_probe_bytes_each_way": state_bytes, "algorithmic_bytes_per_launch": alg, "command": cmd,
     }
     with open(stem + ".json", "w") as fh:
         json.dump(out, fh, indent=1)
@@ -69,7 +73,7 @@ def main(argv):
         fh.write("| scale factors fetch / write | %.4f / %.4f |\n" % (fscale, wscale))
         fh.write("| HBM read bytes per launch | %.4e |\n" % f)
         fh.write("| HBM write bytes per launch | %.4e |\n" % w)
-        fh.write("| total per launch | %.4e (algorithmic %.4e) |\n" % (f + w, 2 * state_bytes))
+        fh.write("| total per launch | %.4e (algorithmic %.4e) |\n" % (f + w, alg))
         fh.write("| kernel source %s sha256[:16] | %s |\n" % (src, sha))
     print(json.dumps(out))
 
