@@ -210,10 +210,11 @@ def main():
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in blocks]
           for _ in range(args.steps)]
 
-    # control bits each block's diagonal sweep skips (from the handle's
-    # statistics, in an untimed step): a sweep with c of them moves 2^-c of
-    # the state, which is what its algorithmic bytes count
-    ctl_bits = [0] * len(blocks)
+    # 16-byte chunks each diagonal block's sweeps visit (from the handle's
+    # statistics, in an untimed step): entries exactly 1 need no visit, and
+    # its algorithmic bytes are 16 in and 16 out per visited chunk
+    diag_chunks = [0] * len(blocks)
+    dispatches = [1] * len(blocks)  # kernel launches per block (a partial diagonal may take several)
 
     def step(timed_index, probe=False):
         sv.reset()
@@ -224,9 +225,11 @@ def main():
                 apply_block(sv, b)
                 e1.record(stream)
             elif probe:
-                c0 = sv.stats()["diag_control_bits"]
+                s0 = sv.stats()
                 apply_block(sv, b)
-                ctl_bits[j] = sv.stats()["diag_control_bits"] - c0
+                s1 = sv.stats()
+                diag_chunks[j] = s1["diag_chunks"] - s0["diag_chunks"]
+                dispatches[j] = s1["launches"] - s0["launches"]
             else:
                 apply_block(sv, b)
         return sv.sample(0x5EED, args.shots)
@@ -243,13 +246,14 @@ def main():
     el = time.perf_counter() - t0
     per_class = {}
     sweep_bytes = 16.0 * (1 << n)
-    block_bytes = [0.0 if c == "layout" else sweep_bytes * 0.5 ** ctl_bits[j] for j, c in enumerate(classes)]
+    block_bytes = [0.0 if c == "layout" else (32.0 * diag_chunks[j] if c == "k_diag" else sweep_bytes)
+                   for j, c in enumerate(classes)]
     for s in range(args.steps):
         for j, c in enumerate(classes):
             if c == "layout":
                 continue
             e0, e1 = ev[s][j]
-            per_class.setdefault(c, []).append((e0.elapsed_time(e1) / 1e3, block_bytes[j]))
+            per_class.setdefault(c, []).append((e0.elapsed_time(e1) / 1e3, block_bytes[j], dispatches[j]))
     log("bench: timed %d steps in %.3f s" % (args.steps, el))
 
     ms_per_step = el / args.steps * 1e3
@@ -258,12 +262,15 @@ def main():
     value = sweeps * args.steps / el
     kernels = {}
     for c, tb in per_class.items():
-        ts = [t for t, _ in tb]
-        by = [b for _, b in tb]
-        gbps = float(np.sum(by)) / float(np.sum(ts)) / 1e9
-        kernels[c] = {"launches": len(ts), "avg_ms": float(np.mean(ts)) * 1e3,
-                      "total_ms_per_step": float(np.sum(ts)) * 1e3 / args.steps,
-                      "bytes_per_launch": float(np.mean(by)), "GBps": gbps, "frac": gbps / HBM_PEAK_GBS}
+        # per kernel launch: HIP events bracket each block, and a block that
+        # takes several launches (partial diagonal sweeps) counts each of them
+        t_all = float(sum(t for t, _, _ in tb))
+        b_all = float(sum(b for _, b, _ in tb))
+        n_all = int(sum(d for _, _, d in tb))
+        gbps = b_all / t_all / 1e9
+        kernels[c] = {"launches": n_all, "blocks": len(tb), "avg_ms": t_all / max(1, n_all) * 1e3,
+                      "total_ms_per_step": t_all * 1e3 / args.steps,
+                      "bytes_per_launch": b_all / max(1, n_all), "GBps": gbps, "frac": gbps / HBM_PEAK_GBS}
     dom = max(kernels, key=lambda c: kernels[c]["total_ms_per_step"])
     achieved = kernels[dom]["GBps"]
     traffic = pmc_traffic(dom)
@@ -336,8 +343,10 @@ def main():
             "parallelism": "single GPU",
         },
         "effective_gbps_per_step": sum(block_bytes) / (ms_per_step / 1e3) / 1e9,
-        "controlled_diagonal_sweeps": sum(1 for c in ctl_bits if c > 0),
-        "diag_control_bits_per_step": int(sum(ctl_bits)),
+        "partial_diagonal_blocks": sum(1 for j, c in enumerate(classes)
+                                       if c == "k_diag" and 32.0 * diag_chunks[j] < sweep_bytes),
+        "diagonal_fraction_swept": (sum(diag_chunks) / (classes.count("k_diag") * (1 << (n - 1)))
+                                    if "k_diag" in classes else None),
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
@@ -792,16 +801,19 @@ def bench_density(args):
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in blocks]
           for _ in range(args.steps)]
 
-    ctl_bits = [0] * len(blocks)  # control bits each diagonal sweep skips (untimed probe step)
+    diag_chunks = [0] * len(blocks)  # 16-byte chunks each diagonal block visits (untimed probe step)
+    dispatches = [1] * len(blocks)   # kernel launches per block
 
     def step(i, probe=False):
         dm.reset()
         for j, b in enumerate(blocks):
             if i is None:
-                c0 = dm.stats()["diag_control_bits"] if probe else 0
+                s0 = dm.stats() if probe else None
                 apply_block(dm, b)
                 if probe:
-                    ctl_bits[j] = dm.stats()["diag_control_bits"] - c0
+                    s1 = dm.stats()
+                    diag_chunks[j] = s1["diag_chunks"] - s0["diag_chunks"]
+                    dispatches[j] = s1["launches"] - s0["launches"]
             else:
                 ev[i][j][0].record(stream)
                 apply_block(dm, b)
@@ -825,15 +837,17 @@ def bench_density(args):
         for j, c in enumerate(classes):
             if c != "layout":
                 per_class.setdefault(c, []).append((ev[s][j][0].elapsed_time(ev[s][j][1]) / 1e3,
-                                                    sweep_bytes * 0.5 ** ctl_bits[j]))
+                                                    32.0 * diag_chunks[j] if c == "k_diag" else sweep_bytes,
+                                                    dispatches[j]))
     kernels = {}
     for c, tb in per_class.items():
-        ts = [t for t, _ in tb]
-        gbps = float(sum(b for _, b in tb)) / float(np.sum(ts)) / 1e9
-        kernels[c] = {"launches": len(ts), "avg_ms": float(np.mean(ts)) * 1e3,
-                      "total_ms_per_step": float(np.sum(ts)) * 1e3 / args.steps,
-                      "bytes_per_launch": float(np.mean([b for _, b in tb])), "GBps": gbps,
-                      "frac": gbps / HBM_PEAK_GBS}
+        t_all = float(sum(t for t, _, _ in tb))
+        b_all = float(sum(b for _, b, _ in tb))
+        n_all = int(sum(d for _, _, d in tb))
+        gbps = b_all / t_all / 1e9
+        kernels[c] = {"launches": n_all, "blocks": len(tb), "avg_ms": t_all / max(1, n_all) * 1e3,
+                      "total_ms_per_step": t_all * 1e3 / args.steps,
+                      "bytes_per_launch": b_all / max(1, n_all), "GBps": gbps, "frac": gbps / HBM_PEAK_GBS}
     dom = max(kernels, key=lambda c: kernels[c]["total_ms_per_step"])
     # the 6-target superoperator sweeps are FP32-MFMA work: 6 * 2^6 flops per amplitude (Gauss form)
     mfma = None

@@ -210,8 +210,8 @@ typedef struct sv_stats {
   int64_t by_variant[6];    /* gate applications per SV_VARIANT_* */
   int64_t permute_sweeps;   /* full-sweep tile permutation passes */
   int64_t layout_only;      /* fused gates that only permute their qubits: applied to the layout map, no sweep */
-  int64_t diag_control_bits; /* over diagonal sweeps: control bits whose clear half was skipped (a sweep
-                                with c of them reads and writes 2^-c of the state) */
+  int64_t diag_chunks;      /* 16-byte chunks the diagonal blocks' sweeps read and wrote (a full sweep is
+                               2^(N-1); entries exactly 1 need no visit, so a block may sweep less) */
 } sv_stats;
 int sv_get_stats(const sv_state *s, sv_stats *out);
 

@@ -134,7 +134,7 @@ class StateVector:
         check(lib().sv_get_stats(self._h, ctypes.byref(s)))
         return {"gate_sweeps": s.gate_sweeps, "swap_half_sweeps": s.swap_half_sweeps, "relabels": s.relabels,
                 "launches": s.launches, "by_variant": list(s.by_variant), "permute_sweeps": s.permute_sweeps,
-                "layout_only": s.layout_only, "diag_control_bits": s.diag_control_bits}
+                "layout_only": s.layout_only, "diag_chunks": s.diag_chunks}
 
     def set_relabel(self, on: bool, low_bits: int = 12, policy: str = "belady"):
         self.set_option(_native.OPT_LAZY_RELABEL, 1 if on else 0)

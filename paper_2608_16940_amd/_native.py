@@ -41,7 +41,7 @@ class sv_stats(ctypes.Structure):
     _fields_ = [("gate_sweeps", ctypes.c_int64), ("swap_half_sweeps", ctypes.c_int64),
                 ("relabels", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("by_variant", ctypes.c_int64 * 6), ("permute_sweeps", ctypes.c_int64),
-                ("layout_only", ctypes.c_int64), ("diag_control_bits", ctypes.c_int64)]
+                ("layout_only", ctypes.c_int64), ("diag_chunks", ctypes.c_int64)]
 
 
 class sv_batch_circuit(ctypes.Structure):

@@ -2,6 +2,8 @@
 // staging, probabilities, norm and sampling.  Host code only; kernels live in
 // sv_kernels.hip and sv_tile.hip.
 #include <algorithm>
+#include <cmath>
+#include <functional>
 #include <climits>
 #include <utility>
 #include <cstdio>
@@ -189,9 +191,86 @@ std::vector<std::pair<int, int>> plan_relabel(const sv_state *s, const int32_t *
   return pairs;
 }
 
-// Lowest physical position a diagonal's control may take: a skipped half
-// then comes in runs of 2^4 amplitudes (128 bytes, whole cache lines).
-constexpr int kDiagControlMinBit = 4;
+// Partial diagonal sweeps.  Amplitudes whose diagonal entry is exactly 1
+// stay as they are, so a diagonal block may sweep only subcubes of the state
+// (target bits held fixed) that together hold every entry that is not 1.
+// Fixed bits sit at physical position 4 or above, so a skipped run is at
+// least 2^4 amplitudes (128 bytes, whole cache lines).  The cover minimises
+// the swept fraction of the state plus kDiagLaunchCost per sweep, over at
+// most kDiagSplitBits candidate bits (the highest targets).
+constexpr int kDiagFixMinBit = 4;
+constexpr int kDiagMaxSweeps = 16;
+constexpr int kDiagSplitBits = 6;
+constexpr double kDiagLaunchCost = 1.0 / 256;  // about 10 us against a 2.5 ms sweep at N=30
+
+struct DiagCover {
+  int nsub = 0;                  // sweeps (0: the table is all ones, nothing to do)
+  uint8_t mask[kDiagMaxSweeps];  // block bits held fixed by each sweep
+  uint8_t val[kDiagMaxSweeps];   // and their values
+};
+
+// Exact minimum over recursive splits: a subcube with no entry other than 1
+// costs nothing, otherwise either one sweep of it or the best split on a
+// free candidate bit.  k <= 8, at most 3^6 subcubes, each scanned once.
+DiagCover diag_cover(int k, const double *matrix, const int32_t *A) {
+  const int D = 1 << k;
+  std::vector<char> one(static_cast<size_t>(D));
+  for (int r = 0; r < D; ++r) one[size_t(r)] = matrix[2 * (r * D + r)] == 1.0 && matrix[2 * (r * D + r) + 1] == 0.0;
+  std::vector<std::pair<int, int>> cand;  // (physical position, block bit), highest positions first
+  for (int j = 0; j < k; ++j)
+    if (A[j] >= kDiagFixMinBit) cand.push_back({A[j], j});
+  std::sort(cand.rbegin(), cand.rend());
+  if (int(cand.size()) > kDiagSplitBits) cand.resize(kDiagSplitBits);
+  uint32_t splittable = 0;
+  for (auto &c : cand) splittable |= 1u << c.second;
+  std::vector<double> cost(65536, -1.0);
+  std::vector<int8_t> choice(65536, 0);  // -2 nothing to do, -1 one sweep, j: split on block bit j
+  std::function<double(uint32_t, uint32_t)> best = [&](uint32_t mask, uint32_t val) -> double {
+    const uint32_t key = (mask << 8) | val;
+    if (cost[key] >= 0) return cost[key];
+    bool any = false;
+    for (int r = 0; r < D && !any; ++r)
+      if ((uint32_t(r) & mask) == val && !one[size_t(r)]) any = true;
+    double c = 0;
+    int8_t ch = -2;
+    if (any) {
+      c = std::ldexp(1.0, -__builtin_popcount(mask)) + kDiagLaunchCost;
+      ch = -1;
+      for (int j = 0; j < k; ++j) {
+        const uint32_t b = 1u << j;
+        if (!(splittable & b) || (mask & b)) continue;
+        const double s = best(mask | b, val) + best(mask | b, val | b);
+        if (s < c - 1e-12) {
+          c = s;
+          ch = int8_t(j);
+        }
+      }
+    }
+    cost[key] = c;
+    choice[key] = ch;
+    return c;
+  };
+  best(0, 0);
+  DiagCover out;
+  std::function<bool(uint32_t, uint32_t)> emit = [&](uint32_t mask, uint32_t val) -> bool {
+    const int8_t ch = choice[(mask << 8) | val];
+    if (ch == -2) return true;
+    if (ch == -1) {
+      if (out.nsub == kDiagMaxSweeps) return false;
+      out.mask[out.nsub] = uint8_t(mask);
+      out.val[out.nsub] = uint8_t(val);
+      ++out.nsub;
+      return true;
+    }
+    const uint32_t b = 1u << ch;
+    return emit(mask | b, val) && emit(mask | b, val | b);
+  };
+  if (!emit(0, 0)) {  // more sweeps than allowed: one full sweep
+    out.nsub = 1;
+    out.mask[0] = out.val[0] = 0;
+  }
+  return out;
+}
 
 // A gate resolved to one kernel launch: the chosen lowering, its physical
 // targets, operands passed by value, and the host bytes of an operand that
@@ -200,8 +279,7 @@ struct Lowered {
   int variant = SV_VARIANT_AUTO;
   int k = 0;
   int32_t A[8] = {0};
-  int nctl = 0;                // diagonal: controls whose clear half the sweep skips
-  int32_t ctl[8] = {0};        //   and their physical positions
+  DiagCover cover;             // diagonal: the subcubes its sweeps visit
   float2 m[256];               // by value: VALU matrix, shuffle 2x2, diagonal table with k <= 4
   bool by_value = false;
   std::vector<char> op;        // device operand bytes (empty when by value)
@@ -252,16 +330,7 @@ int lower(const sv_state *s, const double *matrix, const int32_t *A, int k, bool
       std::vector<float2> d(static_cast<size_t>(D));
       for (int r = 0; r < D; ++r)
         d[r] = make_float2(float(matrix[2 * (r * D + r)]), float(matrix[2 * (r * D + r) + 1]));
-      // controls: targets at which every entry with that bit clear is exactly
-      // 1 (FP64), so those amplitudes stay as they are; only positions from
-      // kDiagControlMinBit up, where the skipped runs span whole cache lines
-      for (int j = 0; j < k; ++j) {
-        if (A[j] < kDiagControlMinBit) continue;
-        bool ctl = true;
-        for (int r = 0; r < D && ctl; ++r)
-          if (!((r >> j) & 1) && (matrix[2 * (r * D + r)] != 1.0 || matrix[2 * (r * D + r) + 1] != 0.0)) ctl = false;
-        if (ctl) L->ctl[L->nctl++] = A[j];
-      }
+      L->cover = diag_cover(k, matrix, A);
       if (k <= 4) {  // small tables ride in the kernel arguments
         L->by_value = true;
         for (int r = 0; r < D; ++r) L->m[r] = d[r];
@@ -326,14 +395,31 @@ int lower(const sv_state *s, const double *matrix, const int32_t *A, int k, bool
 }
 
 // Launch a lowered gate; op_dev holds L.op in device memory when it is not by value.
+// 16-byte chunks a diagonal block's sweeps read and write (a full sweep is 2^(N-1)).
+int64_t diag_chunks(const Lowered &L, int n) {
+  int64_t c = 0;
+  for (int i = 0; i < L.cover.nsub; ++i) c += (int64_t(1) << (n - 1)) >> __builtin_popcount(L.cover.mask[i]);
+  return c;
+}
+
 int launch_lowered(sv_state *s, const Lowered &L, const void *op_dev) {
   const int n = s->n;
   hipError_t e = hipSuccess;
   switch (L.variant) {
     case SV_VARIANT_DIAG:
-      e = L.by_value ? launch_diag(s->amps, n, L.k, L.A, nullptr, L.m, L.nctl, L.ctl, s->st)
-                     : launch_diag(s->amps, n, L.k, L.A, static_cast<const float2 *>(op_dev), nullptr, L.nctl,
-                                   L.ctl, s->st);
+      for (int i = 0; i < L.cover.nsub && e == hipSuccess; ++i) {
+        int32_t fp[8];
+        int nf = 0, fv = 0;
+        for (int j = 0; j < L.k; ++j)
+          if ((L.cover.mask[i] >> j) & 1) {
+            fp[nf] = L.A[j];
+            fv |= ((L.cover.val[i] >> j) & 1) << nf;
+            ++nf;
+          }
+        e = L.by_value ? launch_diag(s->amps, n, L.k, L.A, nullptr, L.m, nf, fp, fv, s->st)
+                       : launch_diag(s->amps, n, L.k, L.A, static_cast<const float2 *>(op_dev), nullptr, nf, fp, fv,
+                                     s->st);
+      }
       break;
     case SV_VARIANT_SHUFFLE: e = launch_1q_shuffle(s->amps, n, L.A[0], L.m, s->st); break;
     case SV_VARIANT_VALU: e = launch_dense_valu(s->amps, n, L.k, L.A, L.m, s->st); break;
@@ -348,9 +434,9 @@ int launch_lowered(sv_state *s, const Lowered &L, const void *op_dev) {
     return SV_ERR_DEVICE;
   }
   s->stats.gate_sweeps += 1;
-  s->stats.launches += 1;
+  s->stats.launches += (L.variant == SV_VARIANT_DIAG) ? L.cover.nsub : 1;
   if (L.variant >= 0 && L.variant < 6) s->stats.by_variant[L.variant] += 1;
-  s->stats.diag_control_bits += L.nctl;
+  if (L.variant == SV_VARIANT_DIAG) s->stats.diag_chunks += diag_chunks(L, n);
   return SV_OK;
 }
 
@@ -1001,7 +1087,7 @@ void add_stats(sv_stats *a, const sv_stats &d) {
   a->launches += d.launches;
   a->layout_only += d.layout_only;
   for (int v = 0; v < 6; ++v) a->by_variant[v] += d.by_variant[v];
-  a->diag_control_bits += d.diag_control_bits;
+  a->diag_chunks += d.diag_chunks;
 }
 
 // After a run: the handle's layout is the one the absorbed permutations leave.
@@ -1073,9 +1159,9 @@ int sv_plan_bind(sv_state *s, const sv_plan *p, void *op_dev, size_t op_bytes, s
         continue;
       }
       b->per_run.gate_sweeps += 1;
-      b->per_run.launches += 1;
+      b->per_run.launches += (L.variant == SV_VARIANT_DIAG) ? L.cover.nsub : 1;
       if (L.variant < 6) b->per_run.by_variant[L.variant] += 1;
-      b->per_run.diag_control_bits += L.nctl;
+      if (L.variant == SV_VARIANT_DIAG) b->per_run.diag_chunks += diag_chunks(L, s->n);
     }
     *out = b;
     return SV_OK;

@@ -66,10 +66,11 @@ hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStre
 
 // Diagonal operator: the 2^k diagonal entries (complex64) in device memory
 // (d_dev), or for k <= 4 from the host by value (d_dev null, d_host set).
-// ctl_phys[0..nctl): distinct physical target positions >= 1 at which the
-// table is exactly 1 wherever that bit is 0; the sweep skips those halves.
+// Partial sweep: fix_phys[0..nfix) are distinct physical positions >= 1 held
+// at the values of bits 0.. of fix_val; only that subcube of the state is
+// read and written (nfix = 0: a full sweep).
 hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *phys_targets, const float2 *d_dev,
-                       const float2 *d_host, int nctl, const int32_t *ctl_phys, hipStream_t st);
+                       const float2 *d_host, int nfix, const int32_t *fix_phys, int fix_val, hipStream_t st);
 // any k <= 8; m_dev: device complex64 row-major matrix.
 hipError_t launch_dense_generic(float2 *psi, int n, int k, const int32_t *phys_targets, const float2 *m_dev,
                                 hipStream_t st);

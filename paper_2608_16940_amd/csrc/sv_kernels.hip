@@ -10,6 +10,7 @@
 // Every index is 64-bit: the state reaches 2^35 amplitudes.
 #include <algorithm>
 #include <cstring>
+#include <utility>
 
 #include "sv_internal.h"
 
@@ -160,28 +161,30 @@ __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ ps
 // stream_chunk; the 2^k table sits in LDS.  One chunk per thread over a full
 // grid (four per thread on a capped, grid-strided launch was 10% slower).
 //
-// Controlled diagonals.  Where the table is exactly 1 whenever some target
-// bit is 0 (that target is a control), the amplitudes with the bit clear are
-// left as they are, so the sweep visits only the chunks with every listed
-// control bit set: work item w becomes a chunk index by inserting a 1 at each
-// control's chunk-bit position (lowest first).  With c controls the pass
-// reads and writes 2^-c of the state.
+// Partial sweeps.  Amplitudes whose table entry is exactly 1 stay as they
+// are, so a sweep may visit only a subcube of the state: some target bits
+// held at fixed values (a controlled phase fixes its control bits to 1).
+// Work item w becomes a chunk index by inserting each fixed bit's value at
+// its chunk-bit position (lowest first); with f fixed bits the pass reads and
+// writes 2^-f of the state.  The host covers the entries that are not 1 with
+// a few such subcubes, one launch each.
 constexpr int kDiagByValue = 16;  // tables up to k = 4 travel in the kernel arguments
 struct DiagArgs {
   int k;
   int tgt[8];  // physical position of block bit j
   int bit0;    // r-bit set by physical bit 0 (0 if bit 0 is not a target)
-  int nctl;    // controls whose clear half is skipped
-  int ctl[8];  // their chunk-bit positions (physical position - 1), ascending
+  int nfix;    // bits held fixed by this partial sweep
+  int fix[8];  // their chunk-bit positions (physical position - 1), ascending
+  int fixval;  // bit i: the value of fix[i]
   float2 small[kDiagByValue];  // the table when dtab is null
 };
 
-__device__ __forceinline__ int64_t insert_one_bit(int64_t x, int p) {
+__device__ __forceinline__ int64_t insert_bit(int64_t x, int p, int64_t v) {
   const int64_t low = x & ((int64_t(1) << p) - 1);
-  return ((x >> p) << (p + 1)) | (int64_t(1) << p) | low;
+  return ((x >> p) << (p + 1)) | (v << p) | low;
 }
 
-// nwork = chunks visited: 2^(N-1) >> nctl.
+// nwork = chunks visited: 2^(N-1) >> nfix.
 template <int UNR>
 __global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, int64_t nwork,
                                                    const float2 *__restrict__ dtab, DiagArgs a) {
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, in
       cc[u] = -1;
       if (lin < nwork) {
         int64_t c = stream_chunk(lin, nwork);
-        for (int i = 0; i < a.nctl; ++i) c = insert_one_bit(c, a.ctl[i]);
+        for (int i = 0; i < a.nfix; ++i) c = insert_bit(c, a.fix[i], (a.fixval >> i) & 1);
         cc[u] = c;
         v[u] = __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(psi4 + c));
       }
@@ -591,8 +594,8 @@ hipError_t launch_1q_shuffle(float2 *psi, int n, int b, const float2 *m, hipStre
 }
 
 hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2 *d_dev, const float2 *d_host,
-                       int nctl, const int32_t *ctl_phys, hipStream_t st) {
-  if (k < 1 || k > 8 || k > n || (!d_dev && (!d_host || k > 4)) || nctl < 0 || nctl > k || (nctl && !ctl_phys))
+                       int nfix, const int32_t *fix_phys, int fix_val, hipStream_t st) {
+  if (k < 1 || k > 8 || k > n || (!d_dev && (!d_host || k > 4)) || nfix < 0 || nfix > k || (nfix && !fix_phys))
     return hipErrorInvalidValue;
   DiagArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -603,17 +606,23 @@ hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2
     a.tgt[j] = A[j];
     if (A[j] == 0) a.bit0 = 1 << j;
   }
-  // controls: distinct targets above physical bit 0, as ascending chunk-bit positions
-  a.nctl = nctl;
-  for (int i = 0; i < nctl; ++i) {
-    if (ctl_phys[i] < 1 || ctl_phys[i] >= n) return hipErrorInvalidValue;
-    a.ctl[i] = ctl_phys[i] - 1;
+  // fixed bits: distinct positions above physical bit 0, as ascending chunk-bit
+  // positions with their values carried along
+  std::pair<int, int> fx[8];
+  for (int i = 0; i < nfix; ++i) {
+    if (fix_phys[i] < 1 || fix_phys[i] >= n) return hipErrorInvalidValue;
+    fx[i] = {fix_phys[i] - 1, (fix_val >> i) & 1};
   }
-  std::sort(a.ctl, a.ctl + nctl);
-  for (int i = 1; i < nctl; ++i)
-    if (a.ctl[i] == a.ctl[i - 1]) return hipErrorInvalidValue;
+  std::sort(fx, fx + nfix);
+  a.nfix = nfix;
+  a.fixval = 0;
+  for (int i = 0; i < nfix; ++i) {
+    if (i > 0 && fx[i].first == fx[i - 1].first) return hipErrorInvalidValue;
+    a.fix[i] = fx[i].first;
+    a.fixval |= fx[i].second << i;
+  }
   constexpr int UNR = 1;
-  const int64_t nwork = (int64_t(1) << (n - 1)) >> nctl;
+  const int64_t nwork = (int64_t(1) << (n - 1)) >> nfix;
   hipLaunchKernelGGL(k_diag<UNR>, dim3(grid_for(nwork, kThreads * UNR, kFullGrid)), dim3(kThreads), 0, st,
                      reinterpret_cast<float4 *>(psi), nwork, d_dev, a);
   return hipGetLastError();
