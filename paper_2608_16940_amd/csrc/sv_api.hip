@@ -211,65 +211,95 @@ struct DiagCover {
 
 // Exact minimum over recursive splits: a subcube with no entry other than 1
 // costs nothing, otherwise either one sweep of it or the best split on a
-// free candidate bit.  k <= 8, at most 3^6 subcubes, each scanned once.
+// free candidate bit.  Subcubes are keyed by the candidate bits they fix
+// (at most 3^6 reachable, 4^6 keys); the memo lives in thread-local arrays
+// stamped per call, so a call allocates nothing (this runs on every
+// diagonal apply).
 DiagCover diag_cover(int k, const double *matrix, const int32_t *A) {
   const int D = 1 << k;
-  std::vector<char> one(static_cast<size_t>(D));
-  for (int r = 0; r < D; ++r) one[size_t(r)] = matrix[2 * (r * D + r)] == 1.0 && matrix[2 * (r * D + r) + 1] == 0.0;
-  std::vector<std::pair<int, int>> cand;  // (physical position, block bit), highest positions first
+  DiagCover out;
+  bool one[256];
+  int nones = 0;
+  for (int r = 0; r < D; ++r) {
+    one[r] = matrix[2 * (r * D + r)] == 1.0 && matrix[2 * (r * D + r) + 1] == 0.0;
+    nones += one[r];
+  }
+  if (nones == D) return out;  // identity: nothing to sweep
+  out.nsub = 1;                // default: one full sweep
+  out.mask[0] = out.val[0] = 0;
+  int cand[8], nc = 0;  // block bits of the highest targets from kDiagFixMinBit up
   for (int j = 0; j < k; ++j)
-    if (A[j] >= kDiagFixMinBit) cand.push_back({A[j], j});
-  std::sort(cand.rbegin(), cand.rend());
-  if (int(cand.size()) > kDiagSplitBits) cand.resize(kDiagSplitBits);
-  uint32_t splittable = 0;
-  for (auto &c : cand) splittable |= 1u << c.second;
-  std::vector<double> cost(65536, -1.0);
-  std::vector<int8_t> choice(65536, 0);  // -2 nothing to do, -1 one sweep, j: split on block bit j
+    if (A[j] >= kDiagFixMinBit) cand[nc++] = j;
+  std::sort(cand, cand + nc, [&](int x, int y) { return A[x] > A[y]; });
+  nc = std::min(nc, kDiagSplitBits);
+  if (nones == 0 || nc == 0) return out;  // every subcube holds entries other than 1
+  // entries as 256-bit sets: those other than 1, and per candidate bit and
+  // value the entries with that bit at that value; a subcube's entries are
+  // the intersection over its fixed bits
+  uint64_t nonone[4] = {0, 0, 0, 0}, sel[kDiagSplitBits][2][4] = {};
+  for (int r = 0; r < D; ++r) {
+    if (!one[r]) nonone[r >> 6] |= uint64_t(1) << (r & 63);
+    for (int c = 0; c < nc; ++c) sel[c][(r >> cand[c]) & 1][r >> 6] |= uint64_t(1) << (r & 63);
+  }
+  constexpr int kKeys = 1 << (2 * kDiagSplitBits);
+  thread_local double cost[kKeys];
+  thread_local int8_t choice[kKeys];  // -2 nothing to do, -1 one sweep, c: split on candidate c
+  thread_local uint32_t stamp[kKeys];
+  thread_local uint32_t gen = 0;
+  if (++gen == 0) {  // stamps wrapped: clear them
+    std::fill(stamp, stamp + kKeys, 0u);
+    gen = 1;
+  }
   std::function<double(uint32_t, uint32_t)> best = [&](uint32_t mask, uint32_t val) -> double {
-    const uint32_t key = (mask << 8) | val;
-    if (cost[key] >= 0) return cost[key];
-    bool any = false;
-    for (int r = 0; r < D && !any; ++r)
-      if ((uint32_t(r) & mask) == val && !one[size_t(r)]) any = true;
+    const uint32_t key = (mask << kDiagSplitBits) | val;
+    if (stamp[key] == gen) return cost[key];
+    uint64_t w[4] = {nonone[0], nonone[1], nonone[2], nonone[3]};
+    for (int q = 0; q < nc; ++q)
+      if ((mask >> q) & 1)
+        for (int i = 0; i < 4; ++i) w[i] &= sel[q][(val >> q) & 1][i];
+    const bool any = (w[0] | w[1] | w[2] | w[3]) != 0;
     double c = 0;
     int8_t ch = -2;
     if (any) {
       c = std::ldexp(1.0, -__builtin_popcount(mask)) + kDiagLaunchCost;
       ch = -1;
-      for (int j = 0; j < k; ++j) {
-        const uint32_t b = 1u << j;
-        if (!(splittable & b) || (mask & b)) continue;
-        const double s = best(mask | b, val) + best(mask | b, val | b);
-        if (s < c - 1e-12) {
-          c = s;
-          ch = int8_t(j);
+      for (int q = 0; q < nc; ++q) {
+        const uint32_t b = 1u << q;
+        if (mask & b) continue;
+        const double sp = best(mask | b, val) + best(mask | b, val | b);
+        if (sp < c - 1e-12) {
+          c = sp;
+          ch = int8_t(q);
         }
       }
     }
+    stamp[key] = gen;
     cost[key] = c;
     choice[key] = ch;
     return c;
   };
   best(0, 0);
-  DiagCover out;
+  DiagCover cv;
   std::function<bool(uint32_t, uint32_t)> emit = [&](uint32_t mask, uint32_t val) -> bool {
-    const int8_t ch = choice[(mask << 8) | val];
+    const int8_t ch = choice[(mask << kDiagSplitBits) | val];
     if (ch == -2) return true;
     if (ch == -1) {
-      if (out.nsub == kDiagMaxSweeps) return false;
-      out.mask[out.nsub] = uint8_t(mask);
-      out.val[out.nsub] = uint8_t(val);
-      ++out.nsub;
+      if (cv.nsub == kDiagMaxSweeps) return false;
+      uint8_t bm = 0, bv = 0;  // back to block bits
+      for (int q = 0; q < nc; ++q) {
+        if ((mask >> q) & 1) bm |= uint8_t(1u << cand[q]);
+        if ((val >> q) & 1) bv |= uint8_t(1u << cand[q]);
+      }
+      cv.mask[cv.nsub] = bm;
+      cv.val[cv.nsub] = bv;
+      ++cv.nsub;
       return true;
     }
     const uint32_t b = 1u << ch;
     return emit(mask | b, val) && emit(mask | b, val | b);
   };
-  if (!emit(0, 0)) {  // more sweeps than allowed: one full sweep
-    out.nsub = 1;
-    out.mask[0] = out.val[0] = 0;
-  }
-  return out;
+  if (emit(0, 0)) return cv;
+  return out;  // more sweeps than allowed: one full sweep
 }
 
 // A gate resolved to one kernel launch: the chosen lowering, its physical
