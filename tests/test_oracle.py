@@ -373,3 +373,45 @@ def test_adam_first_step_is_lr_times_sign():
     np.testing.assert_allclose(newp[0], p[0] - 0.01 * np.sign(g[0]), atol=1e-15)
     np.testing.assert_allclose(newm[0], 0.1 * g[0])
     np.testing.assert_allclose(newv[0], 0.001 * g[0] ** 2)
+
+
+def _ry_rz_product_state(thetas, phis):
+    """Closed form of RY(theta_q) then RZ(phi_q) on every qubit of |0...0>, written out per qubit:
+    qubit q is (cos(theta/2) e^{-i phi/2}, sin(theta/2) e^{+i phi/2}); index bit q = qubit q."""
+    psi = np.ones(1, dtype=np.complex128)
+    for th, ph in zip(thetas, phis):
+        one = np.array([math.cos(th / 2) * np.exp(-0.5j * ph), math.sin(th / 2) * np.exp(0.5j * ph)])
+        psi = np.kron(one, psi)  # the new qubit is the next higher index bit
+    return psi
+
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_probs_of_complex_product_state_closed_form(n):
+    """p_x = |psi_x|^2 (Section IV-E) on amplitudes with nonzero imaginary parts: for the RY-RZ product
+    state, p_x = prod_q cos^2(theta_q/2) or sin^2(theta_q/2) by bit x_q, independent of the phases.
+    Re^2 alone, |psi| or a dropped imaginary part all miss it."""
+    rng = np.random.default_rng(40 + n)
+    th = rng.uniform(0.2, 2.9, n)
+    ph = rng.uniform(0.3, 2.8, n)
+    psi = _ry_rz_product_state(th, ph)
+    assert np.abs(psi.imag).max() > 0.05  # the pin needs complex amplitudes
+    want = np.ones(1 << n)
+    for x in range(1 << n):
+        for q in range(n):
+            want[x] *= math.sin(th[q] / 2) ** 2 if (x >> q) & 1 else math.cos(th[q] / 2) ** 2
+    got = oracle.probs(psi)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+    assert abs(got.sum() - 1.0) < 1e-14
+    # the same state from the gate-by-gate oracle (RY then RZ as 2x2 gates)
+    gates = []
+    for q in range(n):
+        c, s = math.cos(th[q] / 2), math.sin(th[q] / 2)
+        gates.append(W.Gate("ry", (q,), np.array([[c, -s], [s, c]], dtype=np.complex128)))
+        gates.append(W.Gate("rz", (q,), np.diag([np.exp(-0.5j * ph[q]), np.exp(0.5j * ph[q])]), True))
+    np.testing.assert_allclose(oracle.probs(oracle.run(n, gates)), want, rtol=0, atol=1e-14)
+
+
+def test_probs_single_amplitude_values():
+    """p = re^2 + im^2 entry by entry on hand-picked amplitudes (3+4i -> 25, -2i -> 4, 0.5-0.5i -> 0.5)."""
+    psi = np.array([3 + 4j, -2j, 0.5 - 0.5j, 0.0], dtype=np.complex128)
+    np.testing.assert_array_equal(oracle.probs(psi), [25.0, 4.0, 0.5, 0.0])

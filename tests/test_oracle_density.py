@@ -8,7 +8,7 @@ It is checked against what does not come from that code:
 * closed forms of textbook channels: one- and two-qubit depolarizing,
   amplitude damping on a state with a complex phase (target on a high qubit
   too), dephasing, and complete depolarization of every qubit;
-* the vectorised form of Section III-A: sum_i conj(E_i) kron E_i applied by
+* the vectorised form of Section IV-B: sum_i conj(E_i) kron E_i applied by
   the state-vector oracle to vec(rho) on the 2k targets (V, V + N) equals
   vec of the oracle's result (column-major vec, row copies first);
 * trace, Hermiticity and positivity for random CPTP channels.
@@ -105,7 +105,7 @@ def test_dephasing_and_complete_depolarization():
 
 @pytest.mark.parametrize("targets,r", [((2, 0), 3), ((0, 1), 2), ((1,), 4), ((2, 0, 1), 2)])
 def test_vectorised_superoperator_form(targets, r):
-    """Section III-A: vec(sum E rho E^dag) = (sum conj(E) kron E) vec(rho) on targets (V, V + N)."""
+    """Section IV-B: vec(sum E rho E^dag) = (sum conj(E) kron E) vec(rho) on targets (V, V + N)."""
     rng = np.random.default_rng(len(targets) * 10 + r)
     n = 3
     rho = random_mixed(n, rng)
@@ -141,3 +141,36 @@ def test_kraus_sets_are_complete():
                Nz.random_channel((0, 1, 2), 3, rng)]:
         d = 1 << ch.k
         np.testing.assert_allclose(sum(e.conj().T @ e for e in ch.kraus), np.eye(d), atol=1e-13)
+
+
+def test_purity_closed_forms():
+    """purity = Tr(rho^2) = sum_ij |rho_ij|^2 on density matrices written out by hand: a pure state
+    (1), the maximally mixed state on n qubits (2^-n), a dephased superposition with a complex
+    coherence (1/2 + (1-2p)^2/2) and a diagonal mixture.  Tr(rho) (always 1), the diagonal alone,
+    or Re(rho_ij)^2 all fail one of them."""
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(8) + 1j * rng.standard_normal(8)
+    v /= np.linalg.norm(v)
+    assert abs(D.purity(np.outer(v, v.conj())) - 1.0) < 1e-14
+    for n in (1, 2, 4):
+        assert abs(D.purity(np.eye(1 << n, dtype=np.complex128) / (1 << n)) - 2.0 ** -n) < 1e-15
+    for p, phi in [(0.0, 0.7), (0.2, 1.3), (0.5, 2.0)]:
+        c = 0.5 * (1 - 2 * p) * np.exp(-1j * phi)
+        rho = np.array([[0.5, c], [np.conj(c), 0.5]], dtype=np.complex128)
+        assert abs(D.purity(rho) - (0.5 + 0.5 * (1 - 2 * p) ** 2)) < 1e-15
+    w = np.array([0.5, 0.25, 0.125, 0.125])
+    assert abs(D.purity(np.diag(w).astype(np.complex128)) - float((w ** 2).sum())) < 1e-15
+
+
+@pytest.mark.parametrize("p", [0.1, 0.4, 0.75])
+def test_purity_after_depolarizing_closed_form(p):
+    """One-qubit depolarizing of |0><0| through the oracle's channel application: populations
+    1 - 2p/3 and 2p/3, so purity (1 + (1 - 4p/3)^2) / 2; on |+><+| the coherence shrinks by
+    1 - 4p/3 and the purity is the same."""
+    want = (1 + (1 - 4 * p / 3) ** 2) / 2
+    rho = D.apply_channel(D.zero(1), Nz.depolarizing((0,), p).kraus, (0,))
+    assert abs(D.purity(rho) - want) < 1e-14
+    plus = np.full((2, 2), 0.5, dtype=np.complex128)
+    rho = D.apply_channel(plus, Nz.depolarizing((0,), p).kraus, (0,))
+    assert abs(D.purity(rho) - want) < 1e-14
+    assert abs(D.trace(rho) - 1.0) < 1e-14
