@@ -1,6 +1,6 @@
 /*
  * libsv density matrices: the paper's density-matrix wrapper over the same
- * fused-operator interface (Section III-A, the vectorised density matrix).
+ * fused-operator interface (Section IV-B, the vectorised density matrix).
  *
  * An N-qubit density matrix rho (2^N x 2^N) is held as the complex64 vector
  * vec(rho) of 2N logical qubits, stacked column by column: vector index
@@ -21,7 +21,7 @@
  * Hermitian rho).  sv_probs and sv_sample on it would treat vec(rho) as a
  * pure state; the calls below give the measurement distribution instead.
  *
- * The paper's engine range for density matrices is 2 <= N <= 17; a
+ * The paper's engine range for density matrices is 2 <= N <= 17 (Appendix C-A, engine table); a
  * 17-qubit density matrix takes 8 * 4^17 B = 128 GiB.
  */
 #ifndef SV_DENSITY_H_

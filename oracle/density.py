@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY, like the rest of ``oracle``: imported by
 ``tests/``, ``__graft_entry__.smoke`` and the bench's CPU legs, never by the
 product package, and sharing no code with the HIP path.
 
-What it computes (Section III-A, the vectorised density matrix): an N-qubit
+What it computes (Section IV-B, the vectorised density matrix): an N-qubit
 density matrix rho, initially |0..0><0..0|, goes through channels; a channel
 with Kraus operators E_i on the ordered targets V maps rho to
 sum_i E_i rho E_i^dagger, each E_i acting on V with the little-endian target

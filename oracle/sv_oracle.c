@@ -54,9 +54,10 @@ void orc_zero_state(double *psi, int n) {
 }
 
 /*
- * Apply one gate (Section IV-B: the backend applies G in the little-endian
- * order fixed by V; the CPU lowering gathers each group of 2^k amplitudes
- * that share the n-k non-target bits, multiplies by G and writes back).
+ * Apply one gate (Section IV-B semantics; target j of the tuple is bit j of
+ * G's row and column index, Section II).  Each group is the 2^k amplitudes
+ * whose n-k non-target bits agree; the group is read, multiplied by G and
+ * written back in place.
  *
  * For every x whose target bits are all zero, amplitude r of the group is
  * psi[x + sum_j ((r >> j) & 1) << q_j], and the new value of amplitude r is

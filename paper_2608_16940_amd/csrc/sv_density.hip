@@ -1,4 +1,4 @@
-// Density matrices over the fused-operator interface (Section III-A, the
+// Density matrices over the fused-operator interface (Section IV-B, the
 // vectorised density matrix): a handle is a 2N-qubit state holding vec(rho)
 // column-major, channels become 2k-target superoperators applied by
 // sv_apply_fused, and the measurement distribution is the diagonal of rho.

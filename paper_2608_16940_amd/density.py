@@ -1,7 +1,7 @@
 """Density matrices on the fused-operator path (argument marshalling only).
 
 An N-qubit density matrix is a 2N-qubit complex64 state holding vec(rho)
-column by column (index row + 2^N column, Section III-A); channels are
+column by column (index row + 2^N column, Section IV-B); channels are
 applied by ``libsv`` as 2k-target superoperators through the same kernels,
 layout map and planners as state vectors (C-ABI in ``include/sv_density.h``).
 """

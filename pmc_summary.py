@@ -8,7 +8,7 @@ and writes the per-launch HBM bytes of the chosen kernel as JSON and
 markdown.  The JSON carries the hash of the kernel source it was taken on;
 bench.py reports the figure only while that source is unchanged.
 
-usage: python -m paper_2608_16940_amd.pmc_summary FETCH_CSV WRITE_CSV KERNEL_SUBSTR STATE_BYTES OUT_STEM "COMMAND..." [SOURCE [ALG_BYTES]]
+usage: python pmc_summary.py FETCH_CSV WRITE_CSV KERNEL_SUBSTR STATE_BYTES OUT_STEM "COMMAND..." [SOURCE [ALG_BYTES]]
 
 SOURCE is the kernel's source file under paper_2608_16940_amd/csrc (default sv_tile.hip).
 ALG_BYTES is the algorithmic bytes per launch averaged over the counted
@@ -24,7 +24,7 @@ import os
 import statistics
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(ROOT, "paper_2608_16940_amd", "csrc")
 
 

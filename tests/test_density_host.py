@@ -1,7 +1,7 @@
 """Host side of the density-matrix wrapper (no GPU).
 
 * sv_dm_superop builds sum_i conj(E_i) (x) E_i with E_i on the low (row) bits,
-  as the vectorised form of Section III-A fixes; compared with numpy's
+  as the vectorised form of Section IV-B fixes; compared with numpy's
   Kronecker product and, through the oracle, with sum E rho E^dagger;
 * size queries and argument errors;
 * superop_gates: targets (V, V + N) and the diagonal marker.

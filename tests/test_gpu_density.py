@@ -1,4 +1,4 @@
-"""GPU parity of the density-matrix path (Section III-A) against the oracle.
+"""GPU parity of the density-matrix path (Section IV-B) against the oracle.
 
 The GPU applies each channel as the 2k-target superoperator on vec(rho)
 through the same kernels as state vectors; the oracle applies

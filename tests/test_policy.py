@@ -1,8 +1,8 @@
 """Relabel victim policy in the all-frame demand model (host only, no GPU).
 
-Corollary 1 (Section IV-D): with full knowledge of the fused stream, evicting
-the eligible frame whose next use is farthest in the future minimises the
-number of demand promotions.  Pinned by brute force over every eviction
+Corollary 1 (Section IV-D) is the Belady rule for this setting: when the whole
+fused stream is known, choosing as victim the frame that is needed again last
+gives the fewest demand promotions.  Pinned by brute force over every eviction
 choice on tiny streams; first-free and LRU can only do as well or worse.
 """
 import functools
