@@ -121,15 +121,22 @@ int sv_norm(sv_state *s, double *out_host);
  * a zero-probability outcome is never drawn).  Each outcome is decoded through
  * L (Section IV-D): bit q of out_host[s] = logical qubit q.  Deterministic for
  * (state, seed, shots).  Synchronises the stream.
- * Errors: SV_ERR_ARG (shots < 0, null), SV_ERR_STATE (zero total probability).
+ * Errors: SV_ERR_ARG (shots < 0, null), SV_ERR_STATE (zero total probability;
+ * an amplitude that is not finite; ||psi||^2 of 4 or more, whose fixed-point
+ * total T would not fit in 64 bits -- unitarity is not checked elsewhere).
  */
 int sv_sample(sv_state *s, uint64_t seed, int64_t shots, uint64_t *out_host);
 
 /*
  * The same sampler on a caller-supplied FP64 probability array
- * (device, 2^n non-negative entries summing to less than 4, so that the
- * fixed-point total fits in 64 bits), outcome = array index.
+ * (device, 2^n entries), outcome = array index.  Every entry must be finite
+ * and in [0, 4), and the entries must sum to less than 4 (so that the
+ * fixed-point total fits in 64 bits); they need not be normalised.
  * ws_dev >= sv_workspace_bytes(n).  Synchronises `stream`.
+ * Errors: SV_ERR_ARG (null, n out of range, small workspace, an entry that
+ * is negative, not finite or 4 or more, or a total of 4 or more -- found on
+ * the GPU during the CDF build, before any shot is drawn), SV_ERR_STATE (all
+ * entries zero).
  */
 int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots, uint64_t *out_host,
                     void *ws_dev, size_t ws_bytes, void *stream);

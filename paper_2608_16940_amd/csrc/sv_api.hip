@@ -51,6 +51,44 @@ size_t workspace_layout(int n, char *base, Workspace *ws) {
   return off;
 }
 
+LayoutArg identity_layout(int n) {
+  LayoutArg L;
+  std::memset(&L, 0, sizeof(L));
+  for (int q = 0; q < n; ++q) L.pos[q] = int8_t(q);
+  return L;
+}
+
+// The sampler behind the sampling entry points:
+// CDF build, then shots in chunks of `chunk` through ws.shots.  bad_code is
+// the status for inputs the CDF build flags (entries outside [0, 4) or not a
+// number, or a total of 2^64 or more in fixed point).
+int sample_impl(const float2 *psi, const double *probs, int n, const Workspace &ws, int64_t chunk, uint64_t seed,
+                int64_t shots, uint64_t *out_host, const LayoutArg &L, hipStream_t st, int bad_code) {
+  SV_HIP_CHECK(launch_cdf_build(psi, probs, n, ws, st));
+  const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
+  uint64_t total = 0;
+  unsigned bad = 0;
+  SV_HIP_CHECK(hipMemcpyAsync(&total, ws.blocksum + (nb - 1), 8, hipMemcpyDeviceToHost, st));
+  SV_HIP_CHECK(hipMemcpyAsync(&bad, cdf_flag(ws), sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  SV_HIP_CHECK(hipStreamSynchronize(st));
+  if (bad) {
+    set_error(psi ? "state probabilities not finite, or total probability of 4 or more"
+                  : "probabilities must be finite, in [0, 4) and sum to less than 4");
+    return bad_code;
+  }
+  if (total == 0) {
+    set_error("zero total probability");
+    return SV_ERR_STATE;
+  }
+  for (int64_t s0 = 0; s0 < shots; s0 += chunk) {
+    const int64_t cnt = std::min<int64_t>(chunk, shots - s0);
+    SV_HIP_CHECK(launch_shots(psi, probs, n, ws, seed, s0, cnt, L, st));
+    SV_HIP_CHECK(hipMemcpyAsync(out_host + s0, ws.shots, size_t(cnt) * 8, hipMemcpyDeviceToHost, st));
+    SV_HIP_CHECK(hipStreamSynchronize(st));
+  }
+  return SV_OK;
+}
+
 }  // namespace sv
 
 namespace sv {
@@ -733,26 +771,6 @@ int sv_norm(sv_state *s, double *out_host) {
   });
 }
 
-static int sample_impl(const float2 *psi, const double *probs, int n, const Workspace &ws, uint64_t seed,
-                       int64_t shots, uint64_t *out_host, const LayoutArg &L, hipStream_t st) {
-  SV_HIP_CHECK(launch_cdf_build(psi, probs, n, ws, st));
-  const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
-  uint64_t total = 0;
-  SV_HIP_CHECK(hipMemcpyAsync(&total, ws.blocksum + (nb - 1), 8, hipMemcpyDeviceToHost, st));
-  SV_HIP_CHECK(hipStreamSynchronize(st));
-  if (total == 0) {
-    set_error("zero total probability");
-    return SV_ERR_STATE;
-  }
-  for (int64_t s0 = 0; s0 < shots; s0 += kShotChunk) {
-    const int64_t cnt = std::min<int64_t>(kShotChunk, shots - s0);
-    SV_HIP_CHECK(launch_shots(psi, probs, n, ws, seed, s0, cnt, L, st));
-    SV_HIP_CHECK(hipMemcpyAsync(out_host + s0, ws.shots, size_t(cnt) * 8, hipMemcpyDeviceToHost, st));
-    SV_HIP_CHECK(hipStreamSynchronize(st));
-  }
-  return SV_OK;
-}
-
 int sv_sample(sv_state *s, uint64_t seed, int64_t shots, uint64_t *out_host) {
   return guard([&]() -> int {
     if (!s || (!out_host && shots > 0) || shots < 0) {
@@ -760,7 +778,8 @@ int sv_sample(sv_state *s, uint64_t seed, int64_t shots, uint64_t *out_host) {
       return SV_ERR_ARG;
     }
     if (shots == 0) return SV_OK;
-    return sample_impl(s->amps, nullptr, s->n, s->ws, seed, shots, out_host, layout_arg(s), s->st);
+    return sample_impl(s->amps, nullptr, s->n, s->ws, kShotChunk, seed, shots, out_host, layout_arg(s), s->st,
+                       SV_ERR_STATE);
   });
 }
 
@@ -778,10 +797,8 @@ int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots
     if (shots == 0) return SV_OK;
     Workspace ws;
     workspace_layout(n, static_cast<char *>(ws_dev), &ws);
-    LayoutArg L;
-    std::memset(&L, 0, sizeof(L));
-    for (int q = 0; q < n; ++q) L.pos[q] = int8_t(q);
-    return sample_impl(nullptr, probs_dev, n, ws, seed, shots, out_host, L, static_cast<hipStream_t>(stream));
+    return sample_impl(nullptr, probs_dev, n, ws, kShotChunk, seed, shots, out_host, identity_layout(n),
+                       static_cast<hipStream_t>(stream), SV_ERR_ARG);
   });
 }
 

@@ -28,8 +28,12 @@ struct Workspace {
   uint64_t *chunksum = nullptr;  // ceil(nb / 1024) chunk totals
   uint64_t *shots = nullptr;     // kShotChunk decoded outcomes
   double *partials = nullptr;    // kNormPartials FP64 partial sums
-  uint64_t *scalars = nullptr;   // 64 small results
+  uint64_t *scalars = nullptr;   // 64 small results: [0] the FP64 norm, [1] the sampler's bad-input flag
 };
+
+// Set by the CDF build when an entry is outside [0, 4) or not a number, or
+// when the fixed-point total wraps past 2^64 (cleared at the start of each build).
+inline unsigned *cdf_flag(const Workspace &ws) { return reinterpret_cast<unsigned *>(ws.scalars + 1); }
 
 // Bytes needed for an n-qubit workspace; if base != nullptr also fills *ws.
 size_t workspace_layout(int n, char *base, Workspace *ws);
@@ -38,6 +42,13 @@ size_t workspace_layout(int n, char *base, Workspace *ws);
 struct LayoutArg {
   int8_t pos[64];  // pos[q] = physical bit of logical qubit q
 };
+LayoutArg identity_layout(int n);
+
+// The sampler (CDF build, then shots in chunks of `chunk` through ws.shots;
+// psi != nullptr: probabilities of the state, decoded through L; else the
+// caller's array).  Synchronises st.  bad_code: status for flagged inputs.
+int sample_impl(const float2 *psi, const double *probs, int n, const Workspace &ws, int64_t chunk, uint64_t seed,
+                int64_t shots, uint64_t *out_host, const LayoutArg &L, hipStream_t st, int bad_code);
 
 // ------------------------------------------------------------------ error reporting
 void set_error(const std::string &msg);

@@ -332,11 +332,31 @@ __global__ __launch_bounds__(kThreads) void k_norm_final(const double *__restric
 // ------------------------------------------------------------------ sampler
 // Fixed-point probability: q = floor(p * 2^62), exact (power-of-two scaling,
 // truncating conversion).  Integer sums are exact and order-independent, so
-// the block totals do not depend on the reduction tree.
+// the block totals do not depend on the reduction tree.  The scaling needs
+// 0 <= p < 4 (so that q fits in 64 bits); an entry outside that range (NaN
+// included) counts as 0 and raises the caller's bad-input flag, as does any
+// sum that wraps past 2^64 on the way to the total T.
+__device__ __forceinline__ bool q_ok(double p) { return p >= 0.0 && p < 4.0; }
 __device__ __forceinline__ uint64_t fixed_q(double p) { return (uint64_t)(p * 4611686018427387904.0); }
 
+__device__ __forceinline__ uint64_t q_checked(double p, bool &bad) {
+  if (!q_ok(p)) {
+    bad = true;
+    return 0;
+  }
+  return fixed_q(p);
+}
+
 __device__ __forceinline__ uint64_t q_at(const float2 *psi, const double *probs, int64_t i) {
-  return fixed_q(psi ? prob_of(psi[i]) : probs[i]);
+  const double p = psi ? prob_of(psi[i]) : probs[i];
+  return q_ok(p) ? fixed_q(p) : 0ull;
+}
+
+// a + b, noting a carry out of 64 bits
+__device__ __forceinline__ uint64_t add_c(uint64_t a, uint64_t b, bool &wrap) {
+  const uint64_t r = a + b;
+  wrap |= r < a;
+  return r;
 }
 
 // Exact total of each 2^10-entry block; workgroups stride over blocks (the
@@ -347,61 +367,76 @@ __device__ __forceinline__ uint64_t q_at(const float2 *psi, const double *probs,
 // vec = 0 (a caller's probability array not 16-byte aligned) reads entry by entry.
 static_assert((1 << kCdfBlockBits) == 4 * kThreads, "one block = four entries per thread");
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v, bool &wrap) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) {
     const unsigned lo = __shfl_xor(unsigned(v), m), hi = __shfl_xor(unsigned(v >> 32), m);
-    v += (uint64_t(hi) << 32) | lo;
+    v = add_c(v, (uint64_t(hi) << 32) | lo, wrap);
   }
   return v;
 }
 
+__global__ void k_clear_flag(unsigned *flag) { *flag = 0u; }
+
 __global__ __launch_bounds__(kThreads) void k_block_totals(const float2 *__restrict__ psi,
                                                            const double *__restrict__ probs, int64_t dim, int64_t nb,
-                                                           int vec, uint64_t *__restrict__ blocksum) {
+                                                           int vec, uint64_t *__restrict__ blocksum,
+                                                           unsigned *__restrict__ bad_flag) {
   __shared__ uint64_t red[kThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  bool bad = false;
   for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
     const int64_t x0 = (blk << kCdfBlockBits) + 4 * int64_t(threadIdx.x);
-    uint64_t s = 0;
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
     if (vec && x0 + 3 < dim) {
       if (psi) {
         const float4 a = reinterpret_cast<const float4 *>(psi)[x0 / 2];
         const float4 b = reinterpret_cast<const float4 *>(psi)[x0 / 2 + 1];
-        s = fixed_q(prob_of(make_float2(a.x, a.y))) + fixed_q(prob_of(make_float2(a.z, a.w))) +
-            fixed_q(prob_of(make_float2(b.x, b.y))) + fixed_q(prob_of(make_float2(b.z, b.w)));
+        p[0] = prob_of(make_float2(a.x, a.y));
+        p[1] = prob_of(make_float2(a.z, a.w));
+        p[2] = prob_of(make_float2(b.x, b.y));
+        p[3] = prob_of(make_float2(b.z, b.w));
       } else {
         const double2 a = reinterpret_cast<const double2 *>(probs)[x0 / 2];
         const double2 b = reinterpret_cast<const double2 *>(probs)[x0 / 2 + 1];
-        s = fixed_q(a.x) + fixed_q(a.y) + fixed_q(b.x) + fixed_q(b.y);
+        p[0] = a.x;
+        p[1] = a.y;
+        p[2] = b.x;
+        p[3] = b.y;
       }
     } else {
       for (int j = 0; j < 4; ++j)
-        if (x0 + j < dim) s += q_at(psi, probs, x0 + j);
+        if (x0 + j < dim) p[j] = psi ? prob_of(psi[x0 + j]) : probs[x0 + j];
     }
-    s = wave_sum_u64(s);
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s = add_c(s, q_checked(p[j], bad), bad);
+    s = wave_sum_u64(s, bad);
     if (lane == 0) red[wave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
       uint64_t t = 0;
 #pragma unroll
-      for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+      for (int w = 0; w < kThreads / 64; ++w) t = add_c(t, red[w], bad);
       blocksum[blk] = t;
     }
     __syncthreads();
   }
+  if (bad) *bad_flag = 1u;
 }
 
 // Inclusive scan of 1024-element chunks in place (256 threads x 4), chunk total out.
 __global__ __launch_bounds__(kThreads) void k_scan_chunks(uint64_t *__restrict__ v, int64_t nb,
-                                                          uint64_t *__restrict__ chunk_total) {
+                                                          uint64_t *__restrict__ chunk_total,
+                                                          unsigned *__restrict__ bad_flag) {
   __shared__ uint64_t sh[kThreads];
   const int64_t c0 = int64_t(blockIdx.x) * 1024;
+  bool wrap = false;
   uint64_t loc[4];
   uint64_t run = 0;
   for (int i = 0; i < 4; ++i) {
     const int64_t idx = c0 + threadIdx.x * 4 + i;
-    run += (idx < nb) ? v[idx] : 0ull;
+    run = add_c(run, (idx < nb) ? v[idx] : 0ull, wrap);
     loc[i] = run;
   }
   sh[threadIdx.x] = run;
@@ -410,45 +445,54 @@ __global__ __launch_bounds__(kThreads) void k_scan_chunks(uint64_t *__restrict__
   for (int off = 1; off < kThreads; off <<= 1) {
     uint64_t add = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0ull;
     __syncthreads();
-    sh[threadIdx.x] += add;
+    sh[threadIdx.x] = add_c(sh[threadIdx.x], add, wrap);
     __syncthreads();
   }
   const uint64_t excl = (threadIdx.x > 0) ? sh[threadIdx.x - 1] : 0ull;
   for (int i = 0; i < 4; ++i) {
     const int64_t idx = c0 + threadIdx.x * 4 + i;
-    if (idx < nb) v[idx] = loc[i] + excl;
+    if (idx < nb) v[idx] = add_c(loc[i], excl, wrap);
   }
   if (threadIdx.x == kThreads - 1) chunk_total[blockIdx.x] = sh[kThreads - 1];
+  if (wrap) *bad_flag = 1u;
 }
 
 // One workgroup: exclusive scan of the chunk totals in place (sequential per thread slice).
-__global__ __launch_bounds__(kThreads) void k_scan_totals(uint64_t *__restrict__ t, int64_t nc) {
+__global__ __launch_bounds__(kThreads) void k_scan_totals(uint64_t *__restrict__ t, int64_t nc,
+                                                          unsigned *__restrict__ bad_flag) {
   __shared__ uint64_t sh[kThreads];
+  bool wrap = false;
   const int64_t per = (nc + kThreads - 1) / kThreads;
   const int64_t lo = threadIdx.x * per;
   const int64_t hi = lo + per < nc ? lo + per : nc;
   uint64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += t[i];
+  for (int64_t i = lo; i < hi; ++i) s = add_c(s, t[i], wrap);
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int off = 1; off < kThreads; off <<= 1) {
     uint64_t add = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0ull;
     __syncthreads();
-    sh[threadIdx.x] += add;
+    sh[threadIdx.x] = add_c(sh[threadIdx.x], add, wrap);
     __syncthreads();
   }
   uint64_t run = (threadIdx.x > 0) ? sh[threadIdx.x - 1] : 0ull;
   for (int64_t i = lo; i < hi; ++i) {
     const uint64_t v = t[i];
     t[i] = run;
-    run += v;
+    run = add_c(run, v, wrap);
   }
+  if (wrap) *bad_flag = 1u;
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_add(uint64_t *__restrict__ v, int64_t nb,
-                                                       const uint64_t *__restrict__ chunk_excl) {
+                                                       const uint64_t *__restrict__ chunk_excl,
+                                                       unsigned *__restrict__ bad_flag) {
   const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  if (i < nb) v[i] += chunk_excl[i >> 10];
+  if (i < nb) {
+    bool wrap = false;
+    v[i] = add_c(v[i], chunk_excl[i >> 10], wrap);
+    if (wrap) *bad_flag = 1u;
+  }
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): per round two 32x32 -> 64-bit
@@ -680,14 +724,16 @@ hipError_t launch_cdf_build(const float2 *psi, const double *probs, int n, const
   const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
   const int64_t gb = nb < (int64_t(1) << 20) ? nb : (int64_t(1) << 20);
   const int vec = (psi || (reinterpret_cast<uintptr_t>(probs) & 15) == 0) ? 1 : 0;
+  unsigned *flag = cdf_flag(ws);
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, st, flag);
   hipLaunchKernelGGL(k_block_totals, dim3(unsigned(gb)), dim3(kThreads), 0, st, psi, probs, dim, nb, vec,
-                     ws.blocksum);
+                     ws.blocksum, flag);
   const int64_t nc = (nb + 1023) / 1024;
-  hipLaunchKernelGGL(k_scan_chunks, dim3(unsigned(nc)), dim3(kThreads), 0, st, ws.blocksum, nb, ws.chunksum);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(unsigned(nc)), dim3(kThreads), 0, st, ws.blocksum, nb, ws.chunksum, flag);
   if (nc > 1) {
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kThreads), 0, st, ws.chunksum, nc);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kThreads), 0, st, ws.chunksum, nc, flag);
     hipLaunchKernelGGL(k_scan_add, dim3(unsigned((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
-                       ws.blocksum, nb, ws.chunksum);
+                       ws.blocksum, nb, ws.chunksum, flag);
   }
   return hipGetLastError();
 }

@@ -102,3 +102,55 @@ def test_copy_out_physical_and_logical(P, n):
     m = oracle.metrics(oracle.run(n, gates), log.astype(np.complex128))
     assert m["infidelity"] < 1e-5 and m["max_abs"] < 1e-5
     sv.close()
+
+
+def test_sampler_rejects_bad_probabilities(P):
+    """sv_sample_probs: entries must be finite and in [0, 4) and sum to less than 4 (the fixed-point
+    total floor(p * 2^62) summed must fit in 64 bits); the check runs on the GPU during the CDF build."""
+    import torch
+    import paper_2608_16940_amd._native as N
+    n = 11
+    p = np.full(1 << n, 1.0 / (1 << n))
+    for i, v in [(3, -1e-300), (7, np.nan), (0, np.inf), (1, 4.0)]:
+        q = p.copy()
+        q[i] = v
+        with pytest.raises(P.SvError) as e:
+            P.sample_probs(torch.from_numpy(q).cuda(), 1, 10)
+        assert e.value.code == N.SV_ERR_ARG, (i, v)
+    # two entries of 2.0: each is 2^63 in fixed point, the total is exactly 2^64 and wraps
+    q = np.zeros(1 << n)
+    q[[5, 900]] = 2.0
+    with pytest.raises(P.SvError) as e:
+        P.sample_probs(torch.from_numpy(q).cuda(), 1, 10)
+    assert e.value.code == N.SV_ERR_ARG
+    # just under the bound: valid, and only the two nonzero indices are drawn
+    q[900] = np.nextafter(2.0, 0.0)
+    s = P.sample_probs(torch.from_numpy(q).cuda(), 1, 1000)
+    assert set(np.unique(s).tolist()) <= {5, 900}
+    np.testing.assert_array_equal(s, oracle.sample(q, 1, 1000))
+    # unnormalised but valid input samples as the oracle does
+    q = np.random.default_rng(3).random(1 << n) * 3.9 / (1 << n)
+    np.testing.assert_array_equal(P.sample_probs(torch.from_numpy(q).cuda(), 9, 777), oracle.sample(q, 9, 777))
+
+
+def test_sample_rejects_state_outside_the_fixed_point_range(P):
+    """sv_sample on a state whose norm is 4 or more, or with a NaN amplitude, is SV_ERR_STATE
+    (unitarity is not checked by the gate calls, so the sampler guards its fixed-point total)."""
+    import torch
+    import paper_2608_16940_amd._native as N
+    n = 10
+    sv = P.StateVector(n)
+    sv.amps[0] = 2.0  # ||psi||^2 = 4
+    torch.cuda.synchronize()
+    with pytest.raises(P.SvError) as e:
+        sv.sample(1, 10)
+    assert e.value.code == N.SV_ERR_STATE
+    sv.amps[0] = complex(1.0, float("nan"))
+    torch.cuda.synchronize()
+    with pytest.raises(P.SvError) as e:
+        sv.sample(1, 10)
+    assert e.value.code == N.SV_ERR_STATE
+    sv.amps[0] = 1.9
+    torch.cuda.synchronize()
+    assert np.all(sv.sample(1, 50) == 0)
+    sv.close()
