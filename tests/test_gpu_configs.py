@@ -1,0 +1,176 @@
+"""The remaining workloads at full size, in the launch configurations bench.py times.
+
+* the learned plan of the headline circuit at N=30 (brickwork depth 24 + QFT30)
+  against the same complex128 oracle amplitudes as the greedy plan
+  (tests/golden/headline_n30_amplitudes.txt), with the greedy plan measured
+  beside it, so "equal fidelity" is checked where the learned plan is timed;
+* the learned-planner workload: N=34 (128 GiB) brickwork depth 20, learned
+  and greedy plans each followed by the plan of the inverse circuit, back to
+  |0...0> (no oracle fits a 2^34 state: the echo of Section IV-B's exact
+  rewrites is the whole-state check);
+* the 4096-circuit batch in one persistent launch, default and autotuned
+  pack sizes: <Z_0> of every circuit against the oracle's
+  (tests/golden/batch4096_seed0_z0.txt) and 16 amplitudes of every 64th
+  circuit (tests/golden/batch4096_seed0_sample.txt).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2608_16940_amd as P
+    P.lib()
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gather(sv, logical_idx):
+    import torch
+    lay = sv.layout()
+    y = np.zeros_like(np.asarray(logical_idx, dtype=np.int64))
+    for q, pos in enumerate(lay):
+        y |= ((np.asarray(logical_idx, dtype=np.int64) >> q) & 1) << int(pos)
+    sv.sync()
+    return sv.amps[torch.from_numpy(y).to(sv.amps.device)].cpu().numpy().astype(np.complex128)
+
+
+def read_amplitudes(name):
+    idx, vals = [], []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            i, re, im = ln.split()
+            idx.append(int(i))
+            vals.append(complex(float(re), float(im)))
+    return np.array(idx, dtype=np.int64), np.array(vals, dtype=np.complex128)
+
+
+def sample_metrics(got, ref):
+    d = np.abs(got - ref)
+    rel = float(np.sqrt(np.sum(d ** 2) / np.sum(np.abs(ref) ** 2)))
+    fid = abs(np.vdot(ref, got)) ** 2 / (np.vdot(ref, ref).real * np.vdot(got, got).real)
+    return float(d.max()), rel, float(1 - fid)
+
+
+def test_learned_and_greedy_plans_n30_against_oracle_samples(P):
+    """Both plans of the headline circuit meet the same bars against the oracle at 2050 indices;
+    their sampled relative L2 errors are reported side by side."""
+    from paper_2608_16940_amd import costmodel as C
+    n = 30
+    idx, ref = read_amplitudes("headline_n30_amplitudes.txt")
+    gates = W.headline(n, 24, 0)
+    params, _ = C.load()
+    plans = {"greedy": P.Plan.greedy(n, gates, 5), "learned": P.Plan.learned(n, gates, params)}
+    sv = P.StateVector(n)
+    res = {}
+    for name, plan in plans.items():
+        sv.reset()
+        plan.run(sv)
+        mx, rel, inf = sample_metrics(gather(sv, idx), ref)
+        nrm = sv.norm()
+        res[name] = rel
+        say("n30 %s plan (%d blocks): max|d| %.3e rel_l2(sample) %.3e 1-fid(sample) %.3e norm-1 %.3e"
+            % (name, len(plan), mx, rel, inf, nrm - 1))
+        assert mx <= 1e-5 and rel <= 1e-5 and inf <= 1e-5
+        assert abs(nrm - 1) <= 1e-5
+    assert len(plans["learned"]) < len(plans["greedy"])
+    sv.close()
+
+
+def test_learned_and_greedy_echo_n34(P):
+    """N=34 depth-20 brickwork, the learned-planner workload: each plan of the circuit followed by the
+    same planner's plan of the inverse returns |0...0> (fidelity and unnormalised return probability
+    >= 1 - 1e-5, norm within 1e-5), so the learned plan keeps the greedy plan's fidelity at full size."""
+    import torch
+    from paper_2608_16940_amd import costmodel as C
+    n = 34
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    need = (8 << n) + (1 << 30)
+    if free < need:
+        pytest.skip("N=34 needs %.0f GiB of free device memory, %.0f GiB free" % (need / 2**30, free / 2**30))
+    gates = W.brickwork(n, 20, 0)
+    inv = W.inverse(gates)
+    params, _ = C.load()
+    sv = P.StateVector(n)
+    for name in ("learned", "greedy"):
+        if name == "learned":
+            fwd, back = P.Plan.learned(n, gates, params), P.Plan.learned(n, inv, params)
+        else:
+            fwd, back = P.Plan.greedy(n, gates, 5), P.Plan.greedy(n, inv, 5)
+        sv.reset()
+        fwd.run(sv)
+        back.run(sv)
+        nrm = sv.norm()
+        a0 = abs(gather(sv, np.array([0]))[0]) ** 2
+        say("echo n34 %s (%d + %d blocks): fidelity %.12f |<0|psi>|^2 %.12f norm-1 %.3e"
+            % (name, len(fwd), len(back), a0 / nrm, a0, nrm - 1))
+        assert a0 / nrm >= 1 - 1e-5 and a0 >= 1 - 1e-5
+        assert abs(nrm - 1) <= 1e-5
+        s = sv.sample(34, 1000)
+        assert np.all(s == 0)
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
+
+
+def read_batch_golden():
+    z0 = {}
+    with open(os.path.join(GOLDEN, "batch4096_seed0_z0.txt")) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            i, n, ng, z = ln.split()
+            z0[int(i)] = (int(n), int(ng), float(z))
+    amps = {}
+    with open(os.path.join(GOLDEN, "batch4096_seed0_sample.txt")) as f:
+        for ln in f:
+            w = ln.split()
+            if w and w[0] == "amp":
+                amps.setdefault(int(w[1]), []).append((int(w[2]), complex(float(w[3]), float(w[4]))))
+    return z0, amps
+
+
+def test_full_batch_4096_against_oracle(P):
+    """All 4096 circuits of the batch workload in one launch: every <Z_0> within 1e-5 of the oracle's,
+    and 16 amplitudes of every 64th circuit within 1e-5, with the default and the autotuned pack sizes."""
+    from paper_2608_16940_amd import batch as B
+    z0ref, amps = read_batch_golden()
+    circs = W.batch_family(4096, seed=0)
+    assert len(z0ref) == 4096
+    for i, (n, gates) in enumerate(circs):  # the golden file belongs to this circuit family
+        assert z0ref[i][:2] == (n, len(gates)), i
+    zr = np.array([z0ref[i][2] for i in range(4096)])
+    b = B.Batch(circs).allocate()
+    for cfg_name in ("default", "autotuned"):
+        if cfg_name == "default":
+            z0 = b.run()
+        else:
+            cfg, _ = b.autotune()
+            z0 = b.run(cfg)
+        dz = np.abs(np.asarray(z0) - zr)
+        worst_a = 0.0
+        for i, lst in amps.items():
+            st = b.state(i)
+            worst_a = max(worst_a, max(abs(st[x] - v) for x, v in lst))
+        say("batch 4096 %s: max|dZ0| %.3e (circuit %d), sampled max|damp| %.3e over %d circuits"
+            % (cfg_name, dz.max(), int(dz.argmax()), worst_a, len(amps)))
+        assert dz.max() <= 1e-5
+        assert worst_a <= 1e-5

@@ -19,11 +19,17 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 N = 28
-# Relative L2 error bound on the sampled amplitudes.  FP32 MFMA keeps a 2^-24
-# unit roundoff per product; BF16x3 represents each operand by a hi+lo pair of
-# 8-bit significands and drops lo*lo, about 2^-16 relative per product, so one
-# sweep adds ~1.5e-5 and ~150 sweeps random-walk to ~2e-4.
-REL = {"fp32": 1e-5, "bf16x3": 2e-4}
+# Error bounds.  FP32 MFMA keeps a 2^-24 unit roundoff per product.  BF16x3
+# represents each operand by a hi+lo pair of 8-bit significands and drops
+# lo*lo: about 2^-16 relative per product, but the errors of one sweep are
+# independent across amplitudes and partly cancel, and the host split keeps
+# every column norm of the gate exact, so the measured drift is far below the
+# worst case: relative L2 4.3e-5 and |norm - 1| 8e-6 after 168 sweeps at
+# N=28 (k=7), |norm - 1| under 2e-5 for the N=32 echo.  The bars sit at about
+# twice (L2) and 2.5x (norm) those figures, so an order-of-magnitude
+# regression fails.
+REL = {"fp32": 1e-5, "bf16x3": 1e-4}
+NORM = {"fp32": 1e-5, "bf16x3": 5e-5}
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "brickwork_n28_amplitudes.txt")
 
 
@@ -98,7 +104,7 @@ def test_wide_blocks_against_oracle_samples(P, which, prec):
     assert d.max() <= 1e-5
     assert 1 - fid <= 1e-5
     assert rel <= REL[prec]
-    assert abs(nrm - 1) <= REL[prec]
+    assert abs(nrm - 1) <= NORM[prec]
     sv.close()
 
 
@@ -118,9 +124,11 @@ def test_echo_k7(P, prec, n):
     inv.run(sv)
     nrm = sv.norm()
     a0 = abs(gather(sv, np.array([0], dtype=np.int64))[0]) ** 2
-    # fidelity with |0...0> as the oracle defines it: overlap of the normalized states
+    # fidelity with |0...0> as the oracle defines it: overlap of the normalized states;
+    # the unnormalised return probability |<0|psi>|^2 carries the norm drift as well
     f0 = a0 / nrm
-    say("echo n%d k7 %s: fidelity %.9f  norm-1 %.3e" % (n, prec, f0, nrm - 1))
+    say("echo n%d k7 %s: fidelity %.9f  |<0|psi>|^2 %.9f  norm-1 %.3e" % (n, prec, f0, a0, nrm - 1))
     assert f0 >= 1 - 1e-5
-    assert abs(nrm - 1) <= REL[prec]
+    assert abs(nrm - 1) <= NORM[prec]
+    assert a0 >= 1 - 1e-5 - NORM[prec]
     sv.close()
