@@ -205,6 +205,15 @@ const char *sv_last_error(void);
 #define SV_MFMA_OPERAND_GLOBAL 2
 #define SV_MFMA_OPERAND_AUTO 3
 
+/* Order in which the workgroups of an LDS-tiled sweep (MFMA gates, layout
+ * permutations) take tiles.  Consecutive workgroups go to the eight XCDs in
+ * turn; with value x > 0 the three lowest workgroup-index bits move to
+ * tile-index bits x..x+2, so each XCD walks runs of 2^x consecutive tiles
+ * (states with fewer than 2^(x+3) tiles keep the plain order).  0 = plain
+ * order (workgroup i takes tile i); -1 (default) = the order measured
+ * fastest on MI355X. */
+#define SV_OPT_TILE_ORDER 8
+
 int sv_set_option(sv_state *s, int key, int value);
 int sv_get_option(const sv_state *s, int key, int *value);
 

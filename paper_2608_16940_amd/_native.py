@@ -24,6 +24,7 @@ OPT_LAZY_RELABEL = 4
 OPT_LOW_BITS = 5
 OPT_MFMA_OPERAND = 6
 OPT_POLICY = 7
+OPT_TILE_ORDER = 8
 POLICY = {"belady": 0, "first_free": 1, "lru": 2}
 MFMA_OPERAND = {"regs": 0, "lds": 1, "global": 2, "auto": 3}
 

@@ -324,6 +324,7 @@ int lower(const sv_state *s, const double *matrix, const int32_t *A, int k, bool
         set_error("tile geometry failed");
         return SV_ERR_UNSUPPORTED;
       }
+      L->tp.order = s->tile_order;
       // store side: output tile-order bit of position a reads the local bit that
       // held position v on load, and vice versa (a physical bit exchange)
       for (auto &pr : L->relabel) {
@@ -636,6 +637,7 @@ int sv_permute_layout(sv_state *s, const int32_t *new_layout) {
       TilePlan tp;
       tp.n = n;
       tp.s = kTileBits;
+      tp.order = s->tile_order;
       int b = 0;
       for (int p = 0; p < n; ++p)
         if ((smask >> p) & 1) {
@@ -887,6 +889,10 @@ int sv_set_option(sv_state *s, int key, int value) {
         if (value < SV_MFMA_OPERAND_REGS || value > SV_MFMA_OPERAND_AUTO) break;
         s->opsrc = value;
         return SV_OK;
+      case SV_OPT_TILE_ORDER:
+        if (value < -1 || value > 30) break;
+        s->tile_order = value;
+        return SV_OK;
       default:
         break;
     }
@@ -908,6 +914,7 @@ int sv_get_option(const sv_state *s, int key, int *value) {
       case SV_OPT_LAZY_RELABEL: *value = s->lazy; return SV_OK;
       case SV_OPT_LOW_BITS: *value = s->low_bits; return SV_OK;
       case SV_OPT_MFMA_OPERAND: *value = s->opsrc; return SV_OK;
+      case SV_OPT_TILE_ORDER: *value = s->tile_order; return SV_OK;
       case SV_OPT_POLICY: *value = s->policy; return SV_OK;
       default: break;
     }

@@ -106,6 +106,7 @@ hipError_t launch_shots(const float2 *src_state, const double *src_probs, int n,
 // output tile-order index (loc_out == loc_in means no relabel).
 struct TilePlan {
   int n = 0, s = 0, K = 0, M = 0;
+  int order = -1;  // workgroup-to-tile order: -1 the default, 0 plain, x > 0 see tile_order_shift
   uint64_t smask = 0;
   int sbit[32] = {0};
   int loc_in[32] = {0};
@@ -159,6 +160,7 @@ struct sv_state {
   int low_bits = 12;
   int policy = SV_POLICY_BELADY;
   int opsrc = SV_MFMA_OPERAND_AUTO;
+  int tile_order = -1;
   // relabel policy state: planner hints and recency per logical qubit
   bool have_hints = false;
   int64_t next_use[64];

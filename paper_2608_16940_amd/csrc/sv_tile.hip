@@ -76,6 +76,7 @@ struct TileArgs {
   const void *op;
   int64_t ntiles;
   int s;
+  int xs;             // workgroup-to-tile order (tile_of): 0 plain
   int lb_in, lb_out;  // local bit of tile-order bit 0 on load / store
   int sbit[24];
   int loc_in[24];
@@ -88,6 +89,17 @@ struct TileArgs {
 __device__ __forceinline__ int64_t insert_zero_bit(int64_t x, int p) {
   const int64_t low = x & ((int64_t(1) << p) - 1);
   return ((x >> p) << (p + 1)) | low;
+}
+
+// Tile taken by work index w (the workgroup index, plus multiples of the grid
+// size when a workgroup loops).  Workgroups are handed to the eight XCDs in
+// turn, so the three low bits of w name the XCD; with xs > 0 they become tile
+// bits xs..xs+2 and bits 3..xs+2 of w move down, so that each XCD walks runs
+// of 2^xs consecutive tiles.  A bijection on [0, ntiles) when ntiles is a
+// power of two of at least 2^(xs+3) (the host checks).
+__device__ __forceinline__ int64_t tile_of(int64_t w, int xs) {
+  if (xs <= 0) return w;
+  return ((w >> 3) & ((int64_t(1) << xs) - 1)) | ((w & 7) << xs) | ((w >> (xs + 3)) << (xs + 3));
 }
 
 // LDS address of local index lam (amplitude units).  The low K bits (position
@@ -264,12 +276,12 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   float4 v[CHUNKS];  // this tile's 16-byte chunks (global -> LDS)
   int64_t nbase = 0;
   if (PF && int64_t(blockIdx.x) < a.ntiles) {
-    nbase = tile_base(blockIdx.x);
+    nbase = tile_base(tile_of(blockIdx.x, a.xs));
 #pragma unroll
     for (int i = 0; i < CHUNKS; ++i) v[i] = ld_stream(a.psi + nbase + goff_t + a.goff_i[i]);
   }
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const int64_t base = PF ? nbase : tile_base(tile);
+    const int64_t base = PF ? nbase : tile_base(tile_of(tile, a.xs));
     if (!PF) {
 #pragma unroll
       for (int i = 0; i < CHUNKS; ++i) v[i] = ld_stream(a.psi + base + goff_t + a.goff_i[i]);
@@ -288,7 +300,7 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
     }
     __syncthreads();
     if (PF && tile + gridDim.x < a.ntiles) {
-      nbase = tile_base(tile + gridDim.x);
+      nbase = tile_base(tile_of(tile + gridDim.x, a.xs));
 #pragma unroll
       for (int i = 0; i < CHUNKS; ++i) v[i] = ld_stream(a.psi + nbase + goff_t + a.goff_i[i]);
     }
@@ -495,7 +507,7 @@ __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
   }
   const int bout = 1 << a.lb_out;
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    int64_t base = tile;
+    int64_t base = tile_of(tile, a.xs);
 #pragma unroll
     for (int b = 0; b < S; ++b) base = insert_zero_bit(base, a.sbit[b]);
     float4 v[CHUNKS];
@@ -530,12 +542,17 @@ int32_t lam_host(uint64_t v, const int *loc, int s) {
   return o;
 }
 
+// Default workgroup-to-tile order (SV_OPT_TILE_ORDER = -1).
+constexpr int kDefaultTileOrder = 0;
+
 void fill_args(const TilePlan &tp, int nt, int chunks, float2 *psi, const void *op, TileArgs *a) {
   std::memset(a, 0, sizeof(*a));
   a->psi = psi;
   a->op = op;
   a->s = tp.s;
   a->ntiles = int64_t(1) << (tp.n - tp.s);
+  a->xs = tp.order < 0 ? kDefaultTileOrder : tp.order;
+  if (a->xs > 0 && tp.n - tp.s < a->xs + 3) a->xs = 0;
   for (int b = 0; b < tp.s; ++b) {
     a->sbit[b] = tp.sbit[b];
     a->loc_in[b] = tp.loc_in[b];
