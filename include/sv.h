@@ -142,6 +142,30 @@ int sv_sample_probs(const double *probs_dev, int n, uint64_t seed, int64_t shots
                     void *ws_dev, size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code that may not call
+ * hipMalloc or an allocating library routine: tight serving loops,
+ * harnesses that forbid allocation): sv_sample_probs without a workspace.
+ * The sampler's scratch -- CDF block totals, their chunk totals, a chunk of
+ * SV_NOALLOC_SHOT_CHUNK outcomes and a flag, SV_NOALLOC_SCRATCH_BYTES in all
+ * -- is a fixed device array inside the library; each GPU holds its own copy
+ * from the first call on it until the process ends, and the call allocates
+ * nothing.  Arguments, outcomes and errors are those of sv_sample_probs
+ * (outcomes are bit-identical for the same inputs), with n limited to
+ * [1, SV_NOALLOC_MAX_QUBITS].  `stream` must belong to the calling thread's
+ * current device, whose copy of the array is used.  The array keeps the last
+ * call's contents (every call rewrites what it reads).  Calls that overlap on
+ * one GPU -- from several host threads, or on several streams -- share the
+ * array and race: serialise them.  Synchronises `stream`.
+ * Errors: SV_ERR_ARG (as sv_sample_probs, or n > SV_NOALLOC_MAX_QUBITS),
+ * SV_ERR_STATE, SV_ERR_DEVICE.
+ */
+#define SV_NOALLOC_MAX_QUBITS 26
+#define SV_NOALLOC_SHOT_CHUNK 65536
+#define SV_NOALLOC_SCRATCH_BYTES 1049600
+int sv_sample_probs_noalloc(const double *probs_dev, int n, uint64_t seed, int64_t shots, uint64_t *out_host,
+                            void *stream);
+
+/*
  * Copy the state to caller-owned host memory (out_host >= 8 * 2^N bytes,
  * complex64 interleaved).  logical_order = 0: physical order, as stored;
  * 1: logical basis order, out[x] = amps[y] with y_{L(q)} = x_q (decoded on the

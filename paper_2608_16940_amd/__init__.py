@@ -13,7 +13,7 @@ import numpy as np
 from . import _native
 from ._native import SvError, check, lib  # noqa: F401
 
-__all__ = ["StateVector", "DensityMatrix", "sample_probs", "workspace_bytes", "SvError"]
+__all__ = ["StateVector", "DensityMatrix", "sample_probs", "sample_probs_noalloc", "workspace_bytes", "SvError"]
 
 
 def _torch():
@@ -168,6 +168,20 @@ def sample_probs(probs_dev, seed: int, shots: int, stream=None) -> np.ndarray:
     check(lib().sv_sample_probs(ctypes.c_void_p(probs_dev.data_ptr()), n, ctypes.c_uint64(seed & (2**64 - 1)),
                                 int(shots), out.ctypes.data_as(_native._u64p), ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel(), sp))
+    return out
+
+
+def sample_probs_noalloc(probs_dev, seed: int, shots: int, stream=None) -> np.ndarray:
+    """sample_probs without a workspace: the library's fixed per-GPU scratch array
+    (n <= 26; concurrent calls on one GPU race and must be serialised)."""
+    torch = _torch()
+    n = int(probs_dev.numel()).bit_length() - 1
+    assert probs_dev.numel() == 1 << n and probs_dev.dtype == torch.float64 and probs_dev.is_cuda
+    sp, _ = _stream_ptr(stream)
+    out = np.empty(int(shots), dtype=np.uint64)
+    check(lib().sv_sample_probs_noalloc(ctypes.c_void_p(probs_dev.data_ptr()), n,
+                                        ctypes.c_uint64(seed & (2**64 - 1)), int(shots),
+                                        out.ctypes.data_as(_native._u64p), sp))
     return out
 
 

@@ -17,6 +17,8 @@ SV_ERR_DEVICE = -2
 SV_ERR_UNSUPPORTED = -3
 SV_ERR_STATE = -4
 
+NOALLOC_MAX_QUBITS = 26
+
 OPT_VARIANT = 1
 OPT_PRECISION = 2
 OPT_MFMA_MIN_K = 3
@@ -73,6 +75,7 @@ SIGNATURES = [
     ("sv_sample", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int64, _u64p]),
     ("sv_sample_probs", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, _u64p, _vp,
                                        ctypes.c_size_t, _vp]),
+    ("sv_sample_probs_noalloc", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, _u64p, _vp]),
     ("sv_sync", ctypes.c_int, [_vp]),
     ("sv_copy_out", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     ("sv_dm_state_bytes", ctypes.c_size_t, [ctypes.c_int]),
