@@ -22,7 +22,8 @@
 extern "C" {
 #endif
 
-#define SV_MLP_FEATURES 10 /* N, k, 7 sorted physical target positions (padded), sparsity */
+#define SV_MLP_FEATURES 12 /* N, k, 7 sorted physical target positions (padded), diagonal flag,
+                              swept fraction and launches of a diagonal block (sv_plan.h) */
 #define SV_MLP_HIDDEN 64
 
 int sv_mlp_param_count(int nin, int hid);

@@ -51,19 +51,32 @@ int sv_plan_greedy(int n_qubits, int n_gates, const int32_t *ks, const int32_t *
  *   score = SV_SCORE_PAPER:   Gamma = 4^k (dense), 1 (diagonal)
  *   score = SV_SCORE_LEARNED: Gamma = exp(MLP(features) + (N - 30) ln 2), the
  *           cost model's predicted sweep time in ms (the network predicts it
- *           at N=30 scale; sv_mlp.h), params host FP32 (nin, hid).
+ *           at N=30 scale; sv_mlp.h), params host FP32 (nin, hid)
+ *   score = SV_SCORE_ROOFLINE: Gamma = the analytic time of the sweep at
+ *           MI355X's peaks in ms, max(bytes / 8 TB/s, flops / peak) with
+ *           16 B per amplitude visited and the flops of the kernel that runs
+ *           the block (8 * 2^k per amplitude at 78.6 TFLOP/s for k <= 3, the
+ *           same on 157.3 TFLOP/s FP32 MFMA for k = 4, 6 * 2^k there for
+ *           5 <= k <= 7); no parameters
+ * For a diagonal block the learned and analytic scores use what the
+ * streaming lowering sweeps: the block's diagonal (the FP64 product of its
+ * gates' diagonals) is covered by subcubes exactly as sv_apply_fused covers
+ * it (entries exactly 1 need no visit), giving the swept fraction and the
+ * number of launches (sv_diag_sweep_cost); the analytic score charges
+ * fraction + launches / 256 sweeps.
  * Physical positions for the features are the logical qubits (identity
  * layout at planning time).
  */
 #define SV_SCORE_PAPER 0
 #define SV_SCORE_LEARNED 1
+#define SV_SCORE_ROOFLINE 2
 /* flags: SV_PLAN_REORDER first applies a commute-aware reorder (Section
  * IV-C): a gate moves only across gates on disjoint qubits, so each qubit's
  * gate sequence is kept; clusters are grown from the dependency front,
  * taking at each step the ready gate that enlarges the cluster's qubit set
  * least (earliest on ties) while it stays within max(k_max, diag_max). */
 #define SV_PLAN_REORDER 1
-/* flags: SV_PLAN_SEARCH_CAP (learned score only) plans with every dense
+/* flags: SV_PLAN_SEARCH_CAP (learned and analytic scores) plans with every dense
  * width cap c from 4 to k_max, each with diagonal cap min(c, diag_max) and
  * diag_max, and keeps the plan of least predicted total time. */
 #define SV_PLAN_SEARCH_CAP 2
@@ -78,10 +91,28 @@ int sv_plan_dp(int n_qubits, int n_gates, const int32_t *ks, const int32_t *targ
 /*
  * Cost-model features of one fused sweep (SV_MLP_FEATURES floats): N/35,
  * k/8, the k physical target positions sorted ascending divided by 35 and
- * padded with -0.25 to seven slots, and 1 if the block is diagonal (it then
- * takes the streaming diagonal lowering) else 0.
+ * padded with -0.25 to seven slots, 1 if the block is diagonal (it then
+ * takes the streaming diagonal lowering) else 0, and for a diagonal block
+ * the fraction of the state its sweeps visit and its launch count / 16
+ * (dense blocks: 1 and 1/16).  swept_fraction in [0, 1], launches in
+ * [0, 64] (see sv_diag_sweep_cost).  Errors: SV_ERR_ARG (k outside [1, 7],
+ * ranges).
  */
-int sv_cost_features(int n_qubits, int k, const int32_t *phys_targets, int diagonal, float *out);
+int sv_cost_features(int n_qubits, int k, const int32_t *phys_targets, int diagonal, double swept_fraction,
+                     int launches, float *out);
+
+/*
+ * What the streaming diagonal lowering sweeps for a diagonal operator (host
+ * only, no GPU): diag = its 2^k entries, complex128 interleaved, entry r for
+ * the basis state whose bit j is the bit at physical position
+ * phys_targets[j].  Entries exactly 1 + 0i need no visit; the exact minimum
+ * cover by subcubes (target bits at position 4 or above held fixed, at most
+ * 16 sweeps) gives *fraction, the share of the state visited, and
+ * *launches, the partial sweeps run (0 and 0 for the identity).  The same
+ * cover sv_apply_fused uses.  Errors: SV_ERR_ARG (k outside [1, 8],
+ * positions outside [0, 64) or repeated).
+ */
+int sv_diag_sweep_cost(int k, const double *diag, const int32_t *phys_targets, double *fraction, int *launches);
 
 /* Number of fused blocks. */
 int sv_plan_num_blocks(const sv_plan *p, int *out);

@@ -223,24 +223,25 @@ class Plan:
 
     @classmethod
     def dp(cls, n: int, gates, k_max: int = 5, diag_max: int = 6, window: int = 64, params=None,
-           nin: int = 10, hid: int = 64, reorder: bool = False, search_cap: bool = False,
-           repeat: bool = False) -> "Plan":
-        """Windowed DP fusion: paper score (params None) or learned sweep-time score (MLP params);
-        reorder=True first applies the commute-aware reorder; search_cap=True lets the learned
-        score pick the dense width cap (4..k_max); repeat=True reruns reorder-and-fuse on the
-        blocks, at most four rounds in all."""
+           nin: int = 12, hid: int = 64, reorder: bool = False, search_cap: bool = False,
+           repeat: bool = False, score: str = None) -> "Plan":
+        """Windowed DP fusion on a block score: "paper" (4^k / 1), "learned" (the MLP's predicted
+        sweep time; params) or "roofline" (the analytic sweep time at MI355X's peaks); the default
+        is learned when params are given, else paper.  reorder=True first applies the
+        commute-aware reorder; search_cap=True lets a time score pick the dense width cap
+        (4..k_max); repeat=True reruns reorder-and-fuse on the blocks, at most four rounds in all."""
         ks, tg, mats, dg = cls._flat(gates)
         h = ctypes.c_void_p()
-        if params is None:
-            score, pp = 0, None
-        else:
-            score = 1
+        if score is None:
+            score = "paper" if params is None else "learned"
+        pp = None
+        if score == "learned":
             params = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
             pp = params.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         check(lib().sv_plan_dp(int(n), len(gates), ks.ctypes.data_as(_native._i32p),
                                tg.ctypes.data_as(_native._i32p), mats.ctypes.data_as(_native._dp),
                                dg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), int(k_max), int(diag_max),
-                               int(window), score, pp, int(nin), int(hid),
+                               int(window), _native.SCORE[score], pp, int(nin), int(hid),
                                (1 if reorder else 0) | (2 if search_cap else 0) | (4 if repeat else 0),
                                ctypes.byref(h)))
         return cls(h, int(n))
@@ -262,7 +263,14 @@ class Plan:
             plan.swaps_inserted = plan.add_swaps(params, horizon, margin)
         return plan
 
-    def add_swaps(self, params, horizon: int = 32, margin: float = 0.25, nin: int = 10, hid: int = 64) -> int:
+    @classmethod
+    def roofline(cls, n: int, gates, k_max: int = 7, window: int = 64) -> "Plan":
+        """The learned planner's pipeline with the analytic score instead of the network (the
+        ablation of the cost model): reorder, DP with the cap search, cross-window merge, four rounds."""
+        return cls.dp(n, gates, k_max=k_max, diag_max=k_max, window=window, reorder=True, search_cap=True,
+                      repeat=True, score="roofline")
+
+    def add_swaps(self, params, horizon: int = 32, margin: float = 0.25, nin: int = 12, hid: int = 64) -> int:
         """Insert layout-swap blocks where the cost model predicts a net gain; returns how many."""
         params = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
         out = ctypes.c_int()

@@ -30,6 +30,8 @@ OPT_TILE_ORDER = 8
 POLICY = {"belady": 0, "first_free": 1, "lru": 2}
 MFMA_OPERAND = {"regs": 0, "lds": 1, "global": 2, "auto": 3}
 
+SCORE = {"paper": 0, "learned": 1, "roofline": 2}
+
 VARIANT = {"auto": 0, "valu": 1, "shuffle": 2, "mfma": 3, "generic": 4, "diag": 5}
 PRECISION = {"fp32": 0, "bf16x3": 1}
 
@@ -128,8 +130,9 @@ SIGNATURES = [
                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(_vp)]),
-    ("sv_cost_features", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int,
-                                        ctypes.POINTER(ctypes.c_float)]),
+    ("sv_cost_features", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
+    ("sv_diag_sweep_cost", ctypes.c_int, [ctypes.c_int, _dp, _i32p, _dp, ctypes.POINTER(ctypes.c_int)]),
     ("sv_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(sv_batch_circuit)]),
     ("sv_batch_run", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(sv_batch_circuit), _vp, ctypes.c_size_t,
                                     ctypes.POINTER(ctypes.c_int64), _dp, _i32p, _vp, ctypes.c_size_t, _vp]),

@@ -22,7 +22,7 @@ import numpy as np
 from . import _native
 from ._native import check, lib
 
-NIN = 10
+NIN = 12
 HID = 64
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "costmodel_weights.json")
 
@@ -36,12 +36,38 @@ def param_count(nin: int = NIN, hid: int = HID) -> int:
     return int(lib().sv_mlp_param_count(nin, hid))
 
 
-def features(n: int, targets, diagonal: bool) -> np.ndarray:
+def features(n: int, targets, diagonal: bool, fraction: float = 1.0, launches: int = 1) -> np.ndarray:
+    """Cost-model features of one sweep (sv_cost_features): a diagonal block also carries the
+    fraction of the state its sweeps visit and its launch count (diag_sweep_cost)."""
     t = np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
     out = np.zeros(NIN, dtype=np.float32)
     check(lib().sv_cost_features(int(n), int(t.size), t.ctypes.data_as(_native._i32p), 1 if diagonal else 0,
+                                 float(fraction), int(launches),
                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
     return out
+
+
+def diag_sweep_cost(diag, phys_targets):
+    """(fraction of the state visited, launches) of the streaming lowering for a diagonal operator
+    whose entry r has bit j at physical position phys_targets[j] (sv_diag_sweep_cost)."""
+    d = np.ascontiguousarray(np.asarray(diag, dtype=np.complex128))
+    t = np.ascontiguousarray(np.asarray(phys_targets, dtype=np.int32))
+    assert d.size == 1 << t.size
+    fr = ctypes.c_double()
+    ln = ctypes.c_int()
+    check(lib().sv_diag_sweep_cost(int(t.size), d.view(np.float64).ctypes.data_as(_native._dp),
+                                   t.ctypes.data_as(_native._i32p), ctypes.byref(fr), ctypes.byref(ln)))
+    return float(fr.value), int(ln.value)
+
+
+def block_features(n: int, block, layout=None) -> np.ndarray:
+    """Features of a plan block at the physical positions of `layout` (identity if None)."""
+    L = list(range(n)) if layout is None else [int(x) for x in layout]
+    ph = [L[q] for q in block["targets"]]
+    if block["diag"]:
+        fr, ln = diag_sweep_cost(np.diag(block["matrix"]), ph)
+        return features(n, ph, True, fr, ln)
+    return features(n, ph, False)
 
 
 def init_params(seed: int = 0, nin: int = NIN, hid: int = HID) -> np.ndarray:
@@ -147,7 +173,10 @@ def train(X: np.ndarray, y: np.ndarray, steps: int = 3000, lr: float = 3e-3, see
 
 # ------------------------------------------------------------------ timing data
 def _random_block(rng, n, k, kind):
-    """A k-qubit operator of the given structural kind on random targets."""
+    """A k-qubit operator of the given structural kind on random targets: dense (Haar-like),
+    diag (random phases on every entry), cdiag (random phases only where c >= 1 chosen target
+    bits are all set, 1 elsewhere: controlled phases, whose sweeps cover part of the state),
+    perm (a phase permutation)."""
     import workloads as W
     pat = rng.integers(0, 5)
     if pat == 4:
@@ -168,10 +197,15 @@ def _random_block(rng, n, k, kind):
         m = W.random_dense(n, k, rng, targets=t).matrix
     else:
         ph = np.exp(1j * rng.uniform(0, 2 * np.pi, d))
+        if kind == "cdiag":
+            c = int(rng.integers(1, k + 1))
+            ctl = rng.choice(k, size=c, replace=False)
+            cmask = int(sum(1 << int(j) for j in ctl))
+            ph = np.where((np.arange(d) & cmask) == cmask, ph, 1.0 + 0j)
         m = np.diag(ph)
         if kind == "perm":
             m = m[rng.permutation(d)]
-    return t, np.ascontiguousarray(m, dtype=np.complex128), kind == "diag"
+    return t, np.ascontiguousarray(m, dtype=np.complex128), kind in ("diag", "cdiag")
 
 
 def collect(n_values, samples_per_n, seed: int = 0, reps: int = 3, device="cuda:0", log=None):
@@ -192,23 +226,32 @@ def collect(n_values, samples_per_n, seed: int = 0, reps: int = 3, device="cuda:
         t0 = time.perf_counter()
         for _ in range(int(cnt)):
             k = int(rng.choice([1, 2, 3, 4, 5, 6, 7], p=[0.08, 0.12, 0.14, 0.2, 0.24, 0.12, 0.1]))
-            kind = str(rng.choice(["dense", "diag", "perm"], p=[0.7, 0.2, 0.1]))
+            kind = str(rng.choice(["dense", "diag", "cdiag", "perm"], p=[0.6, 0.12, 0.18, 0.1]))
             t, m, is_diag = _random_block(rng, int(n), k, kind)
             sv.apply(m, t)
             times = []
             for _ in range(reps):
+                s0 = sv.stats()
                 e0.record()
                 sv.apply(m, t)
                 e1.record()
                 e1.synchronize()
                 times.append(e0.elapsed_time(e1))
+                s1 = sv.stats()
             ms = float(np.median(times))
-            # features use the physical targets at the time of the sweep
+            # features use the physical targets at the time of the sweep, and for a
+            # diagonal block the fraction of the state its sweeps visited and its launches
             L = sv.layout()
             phys = [int(L[q]) for q in t]
-            Xs.append(features(int(n), phys, is_diag))
+            if is_diag:
+                frac = (s1["diag_chunks"] - s0["diag_chunks"]) / float(1 << (int(n) - 1))
+                launches = int(s1["launches"] - s0["launches"])
+                Xs.append(features(int(n), phys, True, frac, launches))
+            else:
+                frac, launches = 1.0, 1
+                Xs.append(features(int(n), phys, False))
             ys.append(math.log(ms) - (int(n) - 30) * math.log(2.0))
-            rows.append((int(n), k, phys, kind, ms))
+            rows.append((int(n), k, phys, kind, ms, frac, launches))
         if log:
             log("collect n=%d samples=%d %.1f s" % (n, cnt, time.perf_counter() - t0))
         sv.close()
@@ -239,7 +282,7 @@ FIT_SAMPLES = [250, 250, 250, 300, 300, 250, 220, 160, 100, 60]
 FIT_REPS = 5  # timed sweeps per row (the median is the row's time)
 
 
-def fit(seed: int = 0, steps: int = 4000, log=print):
+def fit(seed: int = 0, steps: int = 4000, log=print, weights=WEIGHTS, data=DATA):
     """Collect sweep timings at N=24..33, hold out every fifth row, train, save."""
     X, y, rows = collect(FIT_N, FIT_SAMPLES, seed=seed, reps=FIT_REPS, log=log)
     test = np.arange(len(y)) % 5 == 0
@@ -253,12 +296,12 @@ def fit(seed: int = 0, steps: int = 4000, log=print):
             "reps_per_row": FIT_REPS, "timed_sweeps": int(len(y)) * FIT_REPS,
             "train_steps": steps, "train_seconds": tt, "rmse_log_ms_train": rmse_tr, "rmse_log_ms_test": rmse_te,
             "loss_history": hist}
-    save(params, meta=meta)
-    with open(DATA, "w") as f:
+    save(params, path=weights, meta=meta)
+    kinds = {"dense": 0, "diag": 1, "perm": 2, "cdiag": 3}
+    with open(data, "w") as f:
         f.write(",".join(["f%d" % i for i in range(NIN)] + ["log_ms_at_n30", "n", "k", "kind"]) + "\n")
         for xi, yi, r in zip(X, y, rows):
-            f.write(",".join("%.7g" % v for v in xi) + ",%.7g,%d,%d,%d\n" % (yi, r[0], r[1],
-                                                                        {"dense": 0, "diag": 1, "perm": 2}[r[3]]))
+            f.write(",".join("%.7g" % v for v in xi) + ",%.7g,%d,%d,%d\n" % (yi, r[0], r[1], kinds[r[3]]))
     log("fit: rows %d, train RMSE %.3f, held-out RMSE %.3f (log ms), %.1f s training"
         % (len(y), rmse_tr, rmse_te, tt))
     return params, meta
@@ -267,6 +310,9 @@ def fit(seed: int = 0, steps: int = 4000, log=print):
 if __name__ == "__main__":
     import sys
     if len(sys.argv) > 1 and sys.argv[1] == "fit":
-        fit(log=lambda *a: print(*a, flush=True))
+        # optional output paths: fit WEIGHTS_JSON DATA_CSV
+        w = sys.argv[2] if len(sys.argv) > 2 else WEIGHTS
+        d = sys.argv[3] if len(sys.argv) > 3 else DATA
+        fit(log=lambda *a: print(*a, flush=True), weights=w, data=d)
     else:
-        print("usage: python -m paper_2608_16940_amd.costmodel fit")
+        print("usage: python -m paper_2608_16940_amd.costmodel fit [WEIGHTS_JSON DATA_CSV]")

@@ -3,7 +3,6 @@
 // sv_kernels.hip and sv_tile.hip.
 #include <algorithm>
 #include <cmath>
-#include <functional>
 #include <climits>
 #include <utility>
 #include <cstdio>

@@ -6,7 +6,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
-#include <functional>
 
 namespace sv {
 
@@ -28,12 +27,83 @@ struct DiagCover {
   uint8_t val[kDiagMaxSweeps];   // and their values
 };
 
+namespace detail {
+
+// Working state of one cover computation: the entries other than 1 and, per
+// candidate bit and value, the entries with that bit at that value, as
+// 256-bit sets (a subcube's entries are the intersection over its fixed
+// bits); the memo of subcube costs and choices, keyed by the candidate bits
+// a subcube fixes and their values.
+struct CoverWork {
+  static constexpr int kKeys = 1 << (2 * kDiagSplitBits);
+  int nc = 0;
+  int cand[kDiagSplitBits];
+  uint64_t nonone[4];
+  uint64_t sel[kDiagSplitBits][2][4];
+  double cost[kKeys];
+  int8_t choice[kKeys];  // -2 nothing to do, -1 one sweep, c: split on candidate c
+  uint32_t stamp[kKeys];
+  uint32_t gen = 0;
+};
+
+inline double cover_best(CoverWork &w, uint32_t mask, uint32_t val) {
+  const uint32_t key = (mask << kDiagSplitBits) | val;
+  if (w.stamp[key] == w.gen) return w.cost[key];
+  uint64_t s[4] = {w.nonone[0], w.nonone[1], w.nonone[2], w.nonone[3]};
+  for (int q = 0; q < w.nc; ++q)
+    if ((mask >> q) & 1)
+      for (int i = 0; i < 4; ++i) s[i] &= w.sel[q][(val >> q) & 1][i];
+  const bool any = (s[0] | s[1] | s[2] | s[3]) != 0;
+  double c = 0;
+  int8_t ch = -2;
+  if (any) {
+    c = std::ldexp(1.0, -__builtin_popcount(mask)) + kDiagLaunchCost;
+    ch = -1;
+    for (int q = 0; q < w.nc; ++q) {
+      const uint32_t b = 1u << q;
+      if (mask & b) continue;
+      const double sp = cover_best(w, mask | b, val) + cover_best(w, mask | b, val | b);
+      if (sp < c - 1e-12) {
+        c = sp;
+        ch = int8_t(q);
+      }
+    }
+  }
+  w.stamp[key] = w.gen;
+  w.cost[key] = c;
+  w.choice[key] = ch;
+  return c;
+}
+
+inline bool cover_emit(const CoverWork &w, uint32_t mask, uint32_t val, DiagCover &cv) {
+  const int8_t ch = w.choice[(mask << kDiagSplitBits) | val];
+  if (ch == -2) return true;
+  if (ch == -1) {
+    if (cv.nsub == kDiagMaxSweeps) return false;
+    uint8_t bm = 0, bv = 0;  // back to block bits
+    for (int q = 0; q < w.nc; ++q) {
+      if ((mask >> q) & 1) bm |= uint8_t(1u << w.cand[q]);
+      if ((val >> q) & 1) bv |= uint8_t(1u << w.cand[q]);
+    }
+    cv.mask[cv.nsub] = bm;
+    cv.val[cv.nsub] = bv;
+    ++cv.nsub;
+    return true;
+  }
+  const uint32_t b = 1u << ch;
+  return cover_emit(w, mask | b, val, cv) && cover_emit(w, mask | b, val | b, cv);
+}
+
+}  // namespace detail
+
 // Exact minimum over recursive splits: a subcube with no entry other than 1
 // costs nothing, otherwise either one sweep of it or the best split on a
 // free candidate bit.  Subcubes are keyed by the candidate bits they fix
-// (at most 3^6 reachable, 4^6 keys); the memo lives in thread-local arrays
-// stamped per call, so a call allocates nothing (this runs on every
-// diagonal apply).
+// (at most 3^6 reachable, 4^6 keys).  The working state is one thread-local
+// object (53 KB) whose memo is invalidated per call by a generation stamp,
+// and the recursion passes it by reference, so after a thread's first call
+// (whose thread-local storage the runtime may set up) a call allocates
+// nothing; this runs on every diagonal apply.
 inline DiagCover diag_cover(int k, const double *diag, const int32_t *A) {
   const int D = 1 << k;
   DiagCover out;
@@ -52,72 +122,24 @@ inline DiagCover diag_cover(int k, const double *diag, const int32_t *A) {
   std::sort(cand, cand + nc, [&](int x, int y) { return A[x] > A[y]; });
   nc = std::min(nc, kDiagSplitBits);
   if (nones == 0 || nc == 0) return out;  // every subcube holds entries other than 1
-  // entries as 256-bit sets: those other than 1, and per candidate bit and
-  // value the entries with that bit at that value; a subcube's entries are
-  // the intersection over its fixed bits
-  uint64_t nonone[4] = {0, 0, 0, 0}, sel[kDiagSplitBits][2][4] = {};
+  thread_local detail::CoverWork w;
+  if (++w.gen == 0) {  // stamps wrapped: clear them
+    std::fill(w.stamp, w.stamp + detail::CoverWork::kKeys, 0u);
+    w.gen = 1;
+  }
+  w.nc = nc;
+  for (int c = 0; c < nc; ++c) w.cand[c] = cand[c];
+  for (int i = 0; i < 4; ++i) w.nonone[i] = 0;
+  for (int c = 0; c < nc; ++c)
+    for (int v = 0; v < 2; ++v)
+      for (int i = 0; i < 4; ++i) w.sel[c][v][i] = 0;
   for (int r = 0; r < D; ++r) {
-    if (!one[r]) nonone[r >> 6] |= uint64_t(1) << (r & 63);
-    for (int c = 0; c < nc; ++c) sel[c][(r >> cand[c]) & 1][r >> 6] |= uint64_t(1) << (r & 63);
+    if (!one[r]) w.nonone[r >> 6] |= uint64_t(1) << (r & 63);
+    for (int c = 0; c < nc; ++c) w.sel[c][(r >> cand[c]) & 1][r >> 6] |= uint64_t(1) << (r & 63);
   }
-  constexpr int kKeys = 1 << (2 * kDiagSplitBits);
-  thread_local double cost[kKeys];
-  thread_local int8_t choice[kKeys];  // -2 nothing to do, -1 one sweep, c: split on candidate c
-  thread_local uint32_t stamp[kKeys];
-  thread_local uint32_t gen = 0;
-  if (++gen == 0) {  // stamps wrapped: clear them
-    std::fill(stamp, stamp + kKeys, 0u);
-    gen = 1;
-  }
-  std::function<double(uint32_t, uint32_t)> best = [&](uint32_t mask, uint32_t val) -> double {
-    const uint32_t key = (mask << kDiagSplitBits) | val;
-    if (stamp[key] == gen) return cost[key];
-    uint64_t w[4] = {nonone[0], nonone[1], nonone[2], nonone[3]};
-    for (int q = 0; q < nc; ++q)
-      if ((mask >> q) & 1)
-        for (int i = 0; i < 4; ++i) w[i] &= sel[q][(val >> q) & 1][i];
-    const bool any = (w[0] | w[1] | w[2] | w[3]) != 0;
-    double c = 0;
-    int8_t ch = -2;
-    if (any) {
-      c = std::ldexp(1.0, -__builtin_popcount(mask)) + kDiagLaunchCost;
-      ch = -1;
-      for (int q = 0; q < nc; ++q) {
-        const uint32_t b = 1u << q;
-        if (mask & b) continue;
-        const double sp = best(mask | b, val) + best(mask | b, val | b);
-        if (sp < c - 1e-12) {
-          c = sp;
-          ch = int8_t(q);
-        }
-      }
-    }
-    stamp[key] = gen;
-    cost[key] = c;
-    choice[key] = ch;
-    return c;
-  };
-  best(0, 0);
+  detail::cover_best(w, 0, 0);
   DiagCover cv;
-  std::function<bool(uint32_t, uint32_t)> emit = [&](uint32_t mask, uint32_t val) -> bool {
-    const int8_t ch = choice[(mask << kDiagSplitBits) | val];
-    if (ch == -2) return true;
-    if (ch == -1) {
-      if (cv.nsub == kDiagMaxSweeps) return false;
-      uint8_t bm = 0, bv = 0;  // back to block bits
-      for (int q = 0; q < nc; ++q) {
-        if ((mask >> q) & 1) bm |= uint8_t(1u << cand[q]);
-        if ((val >> q) & 1) bv |= uint8_t(1u << cand[q]);
-      }
-      cv.mask[cv.nsub] = bm;
-      cv.val[cv.nsub] = bv;
-      ++cv.nsub;
-      return true;
-    }
-    const uint32_t b = 1u << ch;
-    return emit(mask | b, val) && emit(mask | b, val | b);
-  };
-  if (emit(0, 0)) return cv;
+  if (detail::cover_emit(w, 0, 0, cv)) return cv;
   return out;  // more sweeps than allowed: one full sweep
 }
 

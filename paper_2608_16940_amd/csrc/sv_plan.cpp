@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "sv_diagcover.h"
 #include "sv_guard.h"
 #include "sv_mlp.h"
 
@@ -39,7 +40,84 @@ struct GateView {
   const double *m;
   bool diag;       // eligible for the streaming diagonal lowering: matrix exactly diagonal
   int weight = 1;  // input gates this view stands for (a block of an earlier round)
+  const double *dtab = nullptr;  // a diagonal view of a later round: its 2^k diagonal entries (m is null)
 };
+
+// Diagonal entry r of a diagonal view, complex128.
+inline void diag_entry(const GateView &g, int r, double *re, double *im) {
+  if (g.m) {
+    const int d = 1 << g.k;
+    *re = g.m[2 * (size_t(r) * d + r)];
+    *im = g.m[2 * (size_t(r) * d + r) + 1];
+  } else {
+    *re = g.dtab[2 * r];
+    *im = g.dtab[2 * r + 1];
+  }
+}
+
+// The diagonal of a run of diagonal gates, built one gate at a time: bit j
+// of the table index is qubit q[j] (first-seen order); a gate's entries
+// multiply the table (diagonal operators commute, so the order of the gates
+// does not matter beyond rounding).
+struct SpanDiag {
+  int k = 0;
+  int32_t q[8];
+  double tab[2 * 256];
+  void reset() {
+    k = 0;
+    tab[0] = 1.0;
+    tab[1] = 0.0;
+  }
+  // false when the span would exceed 8 qubits (the table is then unchanged)
+  bool add(const GateView &g) {
+    int loc[8], fresh = 0;
+    for (int j = 0; j < g.k; ++j) {
+      loc[j] = -1;
+      for (int b = 0; b < k; ++b)
+        if (q[b] == g.t[j]) loc[j] = b;
+      if (loc[j] < 0) ++fresh;
+    }
+    if (k + fresh > 8) return false;
+    for (int j = 0; j < g.k; ++j) {
+      if (loc[j] >= 0) continue;
+      const int D = 1 << k;
+      for (int x = 0; x < D; ++x) {  // the new qubit doubles the table
+        tab[2 * (x + D)] = tab[2 * x];
+        tab[2 * (x + D) + 1] = tab[2 * x + 1];
+      }
+      q[k] = g.t[j];
+      loc[j] = k++;
+    }
+    const int D = 1 << k;
+    for (int x = 0; x < D; ++x) {
+      int r = 0;
+      for (int j = 0; j < g.k; ++j) r |= ((x >> loc[j]) & 1) << j;
+      double gr, gi;
+      diag_entry(g, r, &gr, &gi);
+      const double ar = tab[2 * x], ai = tab[2 * x + 1];
+      tab[2 * x] = ar * gr - ai * gi;
+      tab[2 * x + 1] = ar * gi + ai * gr;
+    }
+    return true;
+  }
+};
+
+// What the streaming lowering sweeps for a diagonal block on physical
+// positions A (table index bit j <-> A[j]): the fraction of the state its
+// exact subcube cover visits and the number of launches (0 for an identity).
+struct DiagCost {
+  double fraction = 1.0;
+  int launches = 1;
+};
+
+inline DiagCost diag_sweep_cost(int k, const double *tab, const int32_t *A) {
+  const sv::DiagCover cv = sv::diag_cover(k, tab, A);
+  DiagCost c;
+  c.launches = cv.nsub;
+  c.fraction = 0.0;
+  for (int i = 0; i < cv.nsub; ++i) c.fraction += std::ldexp(1.0, -__builtin_popcount(cv.mask[i]));
+  return c;
+}
 
 bool is_diagonal(const double *m, int k) {
   const int d = 1 << k;
@@ -295,9 +373,11 @@ int sv_plan_free(sv_plan *p) {
   });
 }
 
-int sv_cost_features(int n, int k, const int32_t *A, int diagonal, float *out) {
+int sv_cost_features(int n, int k, const int32_t *A, int diagonal, double swept_fraction, int launches,
+                     float *out) {
   return sv::guard([&]() -> int {
-    if (!A || !out || k < 1 || k > 7 || n < 1 || n > SV_MAX_QUBITS) {
+    if (!A || !out || k < 1 || k > 7 || n < 1 || n > SV_MAX_QUBITS || !(swept_fraction >= 0.0) ||
+        swept_fraction > 1.0 || launches < 0 || launches > 64) {
       sv::set_error("bad feature argument");
       return SV_ERR_ARG;
     }
@@ -308,6 +388,32 @@ int sv_cost_features(int n, int k, const int32_t *A, int diagonal, float *out) {
     out[1] = float(k) / 8.f;
     for (int j = 0; j < 7; ++j) out[2 + j] = (j < k) ? float(s[j]) / 35.f : -0.25f;
     out[9] = diagonal ? 1.f : 0.f;
+    out[10] = diagonal ? float(swept_fraction) : 1.f;
+    out[11] = diagonal ? float(launches) / 16.f : 1.f / 16.f;
+    return SV_OK;
+  });
+}
+
+int sv_diag_sweep_cost(int k, const double *diag, const int32_t *A, double *fraction, int *launches) {
+  return sv::guard([&]() -> int {
+    if (!diag || !A || !fraction || !launches || k < 1 || k > 8) {
+      sv::set_error("bad diagonal-cost argument");
+      return SV_ERR_ARG;
+    }
+    for (int j = 0; j < k; ++j) {
+      if (A[j] < 0 || A[j] >= 64) {
+        sv::set_error("target position out of range");
+        return SV_ERR_ARG;
+      }
+      for (int i = 0; i < j; ++i)
+        if (A[i] == A[j]) {
+          sv::set_error("duplicate target position");
+          return SV_ERR_ARG;
+        }
+    }
+    const DiagCost c = diag_sweep_cost(k, diag, A);
+    *fraction = c.fraction;
+    *launches = c.launches;
     return SV_OK;
   });
 }
@@ -316,23 +422,33 @@ int sv_cost_features(int n, int k, const int32_t *A, int diagonal, float *out) {
 
 namespace {
 
+// Block cost Gamma for the DP.  dc: what a diagonal block's sweeps visit
+// (null: one full sweep).
 struct Scorer {
   int score;
   int n;
   const float *params;
   int nin, hid;
-  std::map<std::vector<int32_t>, double> cache;  // (sorted targets..., diag) -> Gamma
+  std::map<std::vector<int32_t>, double> cache;  // (sorted targets..., diag, cover) -> Gamma
 
-  double operator()(const std::vector<int32_t> &tuple_sorted, bool all_diag) {
+  double operator()(const std::vector<int32_t> &tuple_sorted, bool all_diag, const DiagCost *dc = nullptr) {
     const int k = int(tuple_sorted.size());
     if (score == SV_SCORE_PAPER) return all_diag ? 1.0 : std::ldexp(1.0, 2 * k);
+    DiagCost full;
+    const DiagCost &c = (all_diag && dc) ? *dc : full;
+    if (all_diag && c.launches == 0) return 0.0;  // the product is the identity: nothing runs
+    if (score == SV_SCORE_ROOFLINE) return roofline_ms(k, all_diag, c);
     if (k > 7) return 1e30;
     std::vector<int32_t> key(tuple_sorted);
     key.push_back(all_diag ? 1 : 0);
+    if (all_diag) {
+      key.push_back(int32_t(std::lround(c.fraction * 65536.0)));
+      key.push_back(c.launches);
+    }
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     float f[SV_MLP_FEATURES];
-    sv_cost_features(n, k, tuple_sorted.data(), all_diag ? 1 : 0, f);
+    sv_cost_features(n, k, tuple_sorted.data(), all_diag ? 1 : 0, c.fraction, c.launches, f);
     double y = 0;
     sv_mlp_forward_host(params, nin, hid, f, 1, &y);
     // the model predicts log(ms) at N = 30 scale; a sweep's time grows as 2^N
@@ -340,7 +456,56 @@ struct Scorer {
     cache.emplace(std::move(key), g);
     return g;
   }
+
+  // The analytic score: a sweep's time at MI355X's peaks, the larger of its
+  // HBM time (16 B per amplitude visited, 8 TB/s) and its arithmetic time
+  // (complex multiply-adds of the kernel that runs it: 8 * 2^k flops per
+  // amplitude on the vector ALU at 78.6 TFLOP/s without packed FP32 for
+  // k <= 3, on FP32 MFMA at 157.3 TFLOP/s for k = 4, the three-product
+  // complex form 6 * 2^k for 5 <= k <= 7); a diagonal block costs the
+  // fraction of the state its cover visits plus kDiagLaunchCost of a sweep
+  // per launch.  In ms.
+  double roofline_ms(int k, bool all_diag, const DiagCost &c) const {
+    const double amps = std::ldexp(1.0, n);
+    const double sweep = 16.0 * amps / 8e12 * 1e3;
+    if (all_diag) return sweep * (c.fraction + double(c.launches) * sv::kDiagLaunchCost);
+    double flops, peak;
+    if (k <= 3) {
+      flops = 8.0 * std::ldexp(1.0, k);
+      peak = 78.6e12;
+    } else if (k == 4) {
+      flops = 8.0 * 16.0;
+      peak = 157.3e12;
+    } else if (k <= 7) {
+      flops = 6.0 * std::ldexp(1.0, k);
+      peak = 157.3e12;
+    } else {
+      flops = 8.0 * std::ldexp(1.0, k);
+      peak = 78.6e12;
+    }
+    return std::max(sweep, flops * amps / peak * 1e3);
+  }
 };
+
+// Cost of gates [a, b) as one block: its sorted tuple, diagonal flag and, for
+// a diagonal block, what its cover sweeps (identity layout: physical
+// position = logical qubit at planning time).
+double span_cost(const std::vector<GateView> &gates, size_t a, size_t b, Scorer &gamma) {
+  std::vector<int32_t> tuple;
+  bool diag = true;
+  for (size_t g = a; g < b; ++g) {
+    for (int j = 0; j < gates[g].k; ++j)
+      if (std::find(tuple.begin(), tuple.end(), gates[g].t[j]) == tuple.end()) tuple.push_back(gates[g].t[j]);
+    diag = diag && gates[g].diag;
+  }
+  std::sort(tuple.begin(), tuple.end());
+  if (!diag || gamma.score == SV_SCORE_PAPER || tuple.size() > 8) return gamma(tuple, diag);
+  SpanDiag sd;
+  sd.reset();
+  for (size_t g = a; g < b; ++g) sd.add(gates[g]);
+  const DiagCost dc = diag_sweep_cost(sd.k, sd.tab, sd.q);
+  return gamma(tuple, true, &dc);
+}
 
 struct Span {
   size_t a, b;  // gates [a, b)
@@ -445,17 +610,24 @@ std::vector<std::vector<size_t>> dp_pass(int n, const std::vector<GateView> &vie
       size_t bj = i - 1;
       std::vector<int32_t> set;
       bool all_diag = true;
+      const bool need_cover = gamma.score != SV_SCORE_PAPER;
+      bool have_tab = need_cover;
+      SpanDiag sd;
+      sd.reset();
       for (size_t j = i; j-- > 0;) {
         const GateView &g = gates[w0 + j];
         for (int q = 0; q < g.k; ++q)
           if (std::find(set.begin(), set.end(), g.t[q]) == set.end()) set.push_back(g.t[q]);
         all_diag = all_diag && g.diag;
+        if (have_tab && (!all_diag || !sd.add(g))) have_tab = false;
         const int width = int(set.size());
         const int cap = all_diag ? diag_max : k_max;
         if (width <= cap || j == i - 1) {
           std::vector<int32_t> srt(set);
           std::sort(srt.begin(), srt.end());
-          const double c = D[j] + gamma(srt, all_diag);
+          DiagCost dc;
+          if (all_diag && have_tab) dc = diag_sweep_cost(sd.k, sd.tab, sd.q);
+          const double c = D[j] + gamma(srt, all_diag, all_diag && have_tab ? &dc : nullptr);
           if (c < best) {
             best = c;
             bj = j;
@@ -476,13 +648,12 @@ std::vector<std::vector<size_t>> dp_pass(int n, const std::vector<GateView> &vie
   for (const Span &sp : spans) {
     if (!merged.empty()) {
       Span &last = merged.back();
-      std::vector<int32_t> t1, t2, tm;
-      bool d1, d2, dm;
-      span_info(gates, last.a, last.b, &t1, &d1);
-      span_info(gates, sp.a, sp.b, &t2, &d2);
+      std::vector<int32_t> tm;
+      bool dm;
       span_info(gates, last.a, sp.b, &tm, &dm);
       const int cap = dm ? diag_max : k_max;
-      if (int(tm.size()) <= cap && gamma(tm, dm) < gamma(t1, d1) + gamma(t2, d2)) {
+      if (int(tm.size()) <= cap &&
+          span_cost(gates, last.a, sp.b, gamma) < span_cost(gates, last.a, last.b, gamma) + span_cost(gates, sp.a, sp.b, gamma)) {
         last.b = sp.b;
         continue;
       }
@@ -493,10 +664,7 @@ std::vector<std::vector<size_t>> dp_pass(int n, const std::vector<GateView> &vie
   out.reserve(merged.size());
   double total = 0;
   for (const Span &sp : merged) {
-    std::vector<int32_t> tp;
-    bool dg;
-    span_info(gates, sp.a, sp.b, &tp, &dg);
-    total += gamma(tp, dg);
+    total += span_cost(gates, sp.a, sp.b, gamma);
     std::vector<size_t> m;
     for (size_t i = sp.a; i < sp.b; ++i) m.push_back(order[i]);
     out.push_back(std::move(m));
@@ -522,6 +690,7 @@ Partition dp_rounds(int n, const std::vector<GateView> &gates, int k_max, int di
   std::vector<std::vector<size_t>> members(gates.size());
   for (size_t i = 0; i < gates.size(); ++i) members[i] = {i};
   std::vector<std::vector<int32_t>> tuples;  // target storage of the current round's views
+  std::vector<std::vector<double>> dtabs;    // diagonal tables of the current round's diagonal views
   Partition best;
   const int rounds = (flags & SV_PLAN_REPEAT) ? 4 : 1;
   for (int r = 0; r < rounds; ++r) {
@@ -539,6 +708,7 @@ Partition dp_rounds(int n, const std::vector<GateView> &gates, int k_max, int di
     best.predicted = t;
     if (r + 1 == rounds) break;
     std::vector<std::vector<int32_t>> next_tuples(part.size());
+    std::vector<std::vector<double>> next_dtabs(part.size());
     std::vector<GateView> next_views;
     next_views.reserve(part.size());
     for (size_t b = 0; b < part.size(); ++b) {
@@ -552,9 +722,23 @@ Partition dp_rounds(int n, const std::vector<GateView> &gates, int k_max, int di
         w += views[v].weight;
       }
       std::sort(next_tuples[b].begin(), next_tuples[b].end());
-      next_views.push_back(GateView{int(next_tuples[b].size()), next_tuples[b].data(), nullptr, dg, w});
+      const double *dt = nullptr;
+      if (dg && next_tuples[b].size() <= 8) {
+        // the block's diagonal over its sorted tuple, for the next round's cover costs
+        SpanDiag sd;
+        sd.reset();
+        for (int32_t q : next_tuples[b]) {  // fix the table's bit order to the sorted tuple
+          const double one[4] = {1.0, 0.0, 1.0, 0.0};
+          sd.add(GateView{1, &q, nullptr, true, 0, one});
+        }
+        for (size_t v : part[b]) sd.add(views[v]);
+        next_dtabs[b].assign(sd.tab, sd.tab + 2 * (size_t(1) << sd.k));
+        dt = next_dtabs[b].data();
+      }
+      next_views.push_back(GateView{int(next_tuples[b].size()), next_tuples[b].data(), nullptr, dg, w, dt});
     }
     tuples = std::move(next_tuples);  // the inner buffers (and the views' pointers) stay where they are
+    dtabs = std::move(next_dtabs);
     views = std::move(next_views);
     members = std::move(next_members);
   }
@@ -581,7 +765,7 @@ extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *t
   return sv::guard([&]() -> int {
     if (!out || ngates < 0 || (ngates > 0 && (!ks || !targets || !mats)) || k_max < 1 || k_max > 8 ||
         diag_max < 1 || diag_max > 8 || window < 1 || n < SV_MIN_QUBITS || n > SV_MAX_QUBITS ||
-        (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED) ||
+        (score != SV_SCORE_PAPER && score != SV_SCORE_LEARNED && score != SV_SCORE_ROOFLINE) ||
         (score == SV_SCORE_LEARNED && (!mlp_params || mlp_nin != SV_MLP_FEATURES || mlp_hid < 1))) {
       sv::set_error("bad dp planner argument");
       return SV_ERR_ARG;
@@ -592,7 +776,7 @@ extern "C" int sv_plan_dp(int n, int ngates, const int32_t *ks, const int32_t *t
       return SV_ERR_ARG;
     }
     Scorer gamma{score, n, mlp_params, mlp_nin, mlp_hid, {}};  // one cache for every pass
-    if ((flags & SV_PLAN_SEARCH_CAP) && score == SV_SCORE_LEARNED) {
+    if ((flags & SV_PLAN_SEARCH_CAP) && score != SV_SCORE_PAPER) {
       // The cost model also picks the caps: plan with every dense cap c up to
       // k_max, with the diagonal cap at min(c, diag_max) and at diag_max
       // (diagonal blocks stream at one sweep's cost whatever their width, but

@@ -22,7 +22,8 @@ def C():
 
 def _data(B=300, seed=0):
     rng = np.random.default_rng(seed)
-    X = rng.standard_normal((B, 10)).astype(np.float32)
+    from paper_2608_16940_amd import costmodel as C
+    X = rng.standard_normal((B, C.NIN)).astype(np.float32)
     t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]).astype(np.float32)
     return X, t
 
@@ -90,7 +91,9 @@ def test_learned_plan_parity(C):
 
 
 def test_learned_plan_not_slower_than_greedy(C):
-    """What the trained network gains: end-to-end execute time at N=27, learned DP vs greedy k<=5."""
+    """The learned planner (reorder, DP on predicted times, cap search) against greedy k<=5 in circuit
+    order: execute time at N=27.  Most of this gain comes from wider blocks and the reorder; the
+    network's own share is measured against the analytic score below."""
     import torch
 
     import paper_2608_16940_amd as P
@@ -164,4 +167,57 @@ def test_layout_swap_from_the_model_runs_and_pays(C):
     with pytest.raises(P.SvError) as e:
         swp.bind(sv)
     assert e.value.code == N.SV_ERR_UNSUPPORTED
+    sv.close()
+
+
+def test_network_vs_analytic_score_same_pipeline(C):
+    """Ablation of the cost model: the same reorder, windowed DP, cross-window merge, cap search and
+    four rounds with Gamma = the MLP's predicted sweep time or Gamma = the analytic roofline time
+    (SV_SCORE_ROOFLINE).  At N=28 (brickwork depth 16, seed 0) both plans are checked against the
+    oracle amplitudes and timed.  The measured margin is reported; the test requires both to beat
+    greedy k<=5 by 2x and to lie within 10% of each other (at N=30 and N=34 the analytic score's
+    plans were 0.8% and 2.0% faster, so the trained network shows no gain over it here)."""
+    import torch
+
+    import paper_2608_16940_amd as P
+    n = 28
+    params, _ = C.load()
+    gates = W.brickwork(n, 16, 0)
+    golden = os.path.join(os.path.dirname(__file__), "golden", "brickwork_n28_amplitudes.txt")
+    idx, ref = [], []
+    with open(golden) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            i, re, im = ln.split()
+            idx.append(int(i))
+            ref.append(complex(float(re), float(im)))
+    idx, ref = np.array(idx, dtype=np.int64), np.array(ref)
+    plans = {"greedy": P.Plan.greedy(n, gates, 5), "network": P.Plan.learned(n, gates, params, swaps=False),
+             "analytic": P.Plan.roofline(n, gates)}
+    sv = P.StateVector(n)
+    t = {}
+    for name, plan in plans.items():
+        ts = []
+        for _ in range(3):
+            sv.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.run(sv)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t[name] = sorted(ts)[1]
+        lay = sv.layout()
+        y = np.zeros_like(idx)
+        for q, pos in enumerate(lay):
+            y |= ((idx >> q) & 1) << int(pos)
+        got = sv.amps[torch.from_numpy(y).to(sv.amps.device)].cpu().numpy().astype(np.complex128)
+        d = np.abs(got - ref)
+        rel = float(np.sqrt(np.sum(d ** 2) / np.sum(np.abs(ref) ** 2)))
+        print("N=28 %s: %d blocks, %.1f ms, rel_l2(sample) %.2e" % (name, len(plan), t[name] * 1e3, rel), flush=True)
+        assert d.max() <= 1e-5 and rel <= 1e-5
+    margin = 1 - t["network"] / t["analytic"]
+    print("network margin over the analytic score: %+.1f%%" % (100 * margin), flush=True)
+    assert t["network"] < 0.5 * t["greedy"] and t["analytic"] < 0.5 * t["greedy"]
+    assert abs(margin) <= 0.10
     sv.close()
