@@ -14,8 +14,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sv_api.hip", "sv_kernels.hip", "sv_tile.hip", "sv_plan.cpp", "sv_batch.hip", "sv_mlp.hip", "sv_density.hip",
-           "sv_noalloc.hip"]
+SOURCES = ["sv_api.hip", "sv_kernels.hip", "sv_tile.hip", "sv_plan.cpp", "sv_batch.hip", "sv_mlp.hip", "sv_density.hip", "sv_batch_host.cpp",
+           "sv_mlp_host.cpp", "sv_host.cpp", "sv_noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

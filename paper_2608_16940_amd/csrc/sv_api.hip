@@ -17,12 +17,8 @@
 namespace sv {
 
 namespace {
-thread_local std::string g_err;
-
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
-
-void set_error(const std::string &msg) { g_err = msg; }
 
 size_t workspace_layout(int n, char *base, Workspace *ws) {
   const int64_t nb = n > kCdfBlockBits ? (int64_t(1) << (n - kCdfBlockBits)) : 1;
@@ -91,33 +87,6 @@ int sample_impl(const float2 *psi, const double *probs, int n, const Workspace &
 }  // namespace sv
 
 namespace sv {
-
-// True when G maps each basis state |c> to |pi(c)>, pi moving bit j of c to
-// bit perm[j] (a permutation of the block's qubits), with exact 0/1 entries.
-bool qubit_permutation(const double *G, int k, int *perm) {
-  const int D = 1 << k;
-  for (int i = 0; i < D * D; ++i)
-    if (G[2 * i + 1] != 0.0 || (G[2 * i] != 0.0 && G[2 * i] != 1.0)) return false;
-  int used = 0;
-  for (int j = 0; j < k; ++j) {
-    int row = -1;
-    for (int r = 0; r < D; ++r)
-      if (G[2 * (r * D + (1 << j))] == 1.0) {
-        if (row >= 0) return false;
-        row = r;
-      }
-    if (row <= 0 || (row & (row - 1)) || (used & row)) return false;
-    used |= row;
-    perm[j] = __builtin_ctz(unsigned(row));
-  }
-  for (int c = 0; c < D; ++c) {
-    int r = 0;
-    for (int j = 0; j < k; ++j) r |= ((c >> j) & 1) << perm[j];
-    for (int rr = 0; rr < D; ++rr)
-      if (G[2 * (rr * D + c)] != (rr == r ? 1.0 : 0.0)) return false;
-  }
-  return true;
-}
 
 }  // namespace sv
 
@@ -425,8 +394,6 @@ int apply_physical(sv_state *s, const double *matrix, const int32_t *A, int k) {
 
 extern "C" {
 
-const char *sv_last_error(void) { return g_err.c_str(); }
-
 size_t sv_workspace_bytes(int n_qubits) {
   if (!valid_n(n_qubits)) return 0;
   return workspace_layout(n_qubits, nullptr, nullptr);
@@ -435,7 +402,7 @@ size_t sv_workspace_bytes(int n_qubits) {
 int sv_alloc(sv_state **out, int n, void *amps_dev, size_t amps_bytes, void *ws_dev, size_t ws_bytes,
              void *stream) {
   return guard([&]() -> int {
-    g_err.clear();
+    clear_error();
     if (!out || !amps_dev || !ws_dev) {
       set_error("null pointer");
       return SV_ERR_ARG;

@@ -11,6 +11,7 @@
 namespace sv {
 
 void set_error(const std::string &msg);
+void clear_error();
 
 // Every exported entry point runs its body through guard(): an exception
 // thrown inside (a failed host allocation, an internal error) becomes an

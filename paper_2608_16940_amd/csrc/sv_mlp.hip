@@ -1,32 +1,22 @@
-// Cost-model MLP: forward, backward and Adam kernels (FP32), plus a host
-// forward for the planner.  Sizes are tiny (4.9k parameters, batches of a
-// few thousand rows): one thread per output element, reductions over the
-// batch in a fixed order so every run gives the same bits.
+// Cost-model MLP: forward, backward and Adam kernels (FP32); the host
+// forward for the planner is in sv_mlp_host.cpp.  Sizes are tiny (5k
+// parameters, batches of a few thousand rows): one thread per output
+// element, reductions over the batch in a fixed order so every run gives
+// the same bits.
 #include <cmath>
 #include <vector>
 
 #include "sv_internal.h"
 #include "sv_mlp.h"
+#include "sv_mlp_layout.h"
 
 namespace sv {
 namespace {
 
 constexpr int kT = 256;
 
-struct Off {
-  int w1, b1, w2, b2, w3, b3, total;
-};
-__host__ __device__ inline Off offsets(int nin, int hid) {
-  Off o;
-  o.w1 = 0;
-  o.b1 = o.w1 + nin * hid;
-  o.w2 = o.b1 + hid;
-  o.b2 = o.w2 + hid * hid;
-  o.w3 = o.b2 + hid;
-  o.b3 = o.w3 + hid;
-  o.total = o.b3 + 1;
-  return o;
-}
+using Off = MlpOffsets;
+inline Off offsets(int nin, int hid) { return mlp_offsets(nin, hid); }
 
 // z[r][u] = sum_i in[r][i] W[i][u] + b[u]; relu_in: apply relu to `in` on read
 __global__ __launch_bounds__(kT) void k_dense(const float *__restrict__ in, int nin, bool relu_in,
@@ -163,28 +153,8 @@ using namespace sv;
 
 extern "C" {
 
-int sv_mlp_param_count(int nin, int hid) { return offsets(nin, hid).total; }
-
-int64_t sv_mlp_cache_floats(int hid, int batch) { return 4 * int64_t(hid) * batch; }
-
 int sv_mlp_forward(const float *params, int nin, int hid, const float *X, int batch, float *y, float *cache,
                    void *stream) {
-  return guard([&]() -> int {
-    if (!params || !X || !y || nin < 1 || hid < 1 || batch < 1 || !cache) {
-      set_error("bad mlp forward argument (cache is required)");
-      return SV_ERR_ARG;
-    }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const Off o = offsets(nin, hid);
-    float *z1 = cache, *z2 = cache + int64_t(hid) * batch;
-    hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, X, nin, false, params + o.w1,
-                       params + o.b1, hid, batch, z1);
-    hipLaunchKernelGGL(k_dense, dim3(blocks(int64_t(batch) * hid)), dim3(kT), 0, st, z1, hid, true, params + o.w2,
-                       params + o.b2, hid, batch, z2);
-    hipLaunchKernelGGL(k_out, dim3(blocks(batch)), dim3(kT), 0, st, z2, hid, params + o.w3, params + o.b3, batch, y);
-    SV_HIP_CHECK(hipGetLastError());
-    return SV_OK;
-  });
   return guard([&]() -> int {
     if (!params || !X || !y || nin < 1 || hid < 1 || batch < 1 || !cache) {
       set_error("bad mlp forward argument (cache is required)");
@@ -242,34 +212,6 @@ int sv_mlp_adam(float *params, const float *grads, float *m, float *v, int count
     hipLaunchKernelGGL(k_adam, dim3(blocks(count)), dim3(kT), 0, static_cast<hipStream_t>(stream), params, grads, m,
                        v, count, lr, beta1, beta2, eps, c1, c2);
     SV_HIP_CHECK(hipGetLastError());
-    return SV_OK;
-  });
-}
-
-int sv_mlp_forward_host(const float *p, int nin, int hid, const float *x, int batch, double *y) {
-  return guard([&]() -> int {
-    if (!p || !x || !y || nin < 1 || hid < 1 || batch < 0) {
-      set_error("bad host mlp argument");
-      return SV_ERR_ARG;
-    }
-    const Off o = offsets(nin, hid);
-    std::vector<double> h1(static_cast<size_t>(hid)), h2(static_cast<size_t>(hid));
-    for (int r = 0; r < batch; ++r) {
-      const float *xr = x + int64_t(r) * nin;
-      for (int u = 0; u < hid; ++u) {
-        double a = p[o.b1 + u];
-        for (int i = 0; i < nin; ++i) a += double(xr[i]) * double(p[o.w1 + i * hid + u]);
-        h1[size_t(u)] = a > 0 ? a : 0;
-      }
-      for (int u = 0; u < hid; ++u) {
-        double a = p[o.b2 + u];
-        for (int i = 0; i < hid; ++i) a += h1[size_t(i)] * double(p[o.w2 + i * hid + u]);
-        h2[size_t(u)] = a > 0 ? a : 0;
-      }
-      double a = p[o.b3];
-      for (int u = 0; u < hid; ++u) a += h2[size_t(u)] * double(p[o.w3 + u]);
-      y[r] = a;
-    }
     return SV_OK;
   });
 }
