@@ -20,7 +20,7 @@ cover visits part of the state counts as one gate-sweep in ``value``;
 on this host (median of three all-core runs, one single-thread run).  After
 the timed region the line also carries ``workloads``: compact records of the
 other workloads (``--workload`` runs one of them in full: learned, batch,
-precision, c1, density), each with its own roofline, and ``paper_context``,
+precision, c1, density, layout), each with its own roofline, and ``paper_context``,
 the paper's own intervals on other hardware.
 """
 import argparse
@@ -264,16 +264,17 @@ def main():
                     help="skip the learned-plan and BF16x3 legs reported after the timed region")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the compact records of the other workloads (c1, precision, batch, learned, "
-                         "density) that the default run appends after the timed region")
+                         "density, layout) that the default run appends after the timed region")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one plain device copy of the state's size "
                          "(reference dispatch for scaling HBM byte counters)")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "learned", "batch", "precision", "c1", "density"],
+                    choices=["headline", "learned", "batch", "precision", "c1", "density", "layout"],
                     help="headline (default): N=30 brickwork+QFT, greedy k<=5; learned: learned-DP vs greedy "
                          "plans at N=34 depth 20; batch: 4096 small circuits in one launch; precision: N=32 "
                          "depth-16 circuit fused to k<=6/7, FP32 vs BF16x3; c1: N=20 gate by gate + 10^4 shots; "
-                         "density: 15-qubit noisy brickwork density matrix (vec(rho) 8 GiB), fused superoperators")
+                         "density: 15-qubit noisy brickwork density matrix (vec(rho) 8 GiB), fused superoperators; "
+                         "layout: the model's layout swap and the lazy relabel at N=30")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -289,7 +290,7 @@ def main():
     import workloads as W
 
     others = {"learned": bench_learned, "batch": bench_batch, "precision": bench_precision, "c1": bench_c1,
-              "density": bench_density}
+              "density": bench_density, "layout": bench_layout}
     if args.workload in others:
         print(json.dumps(others[args.workload](args)), flush=True)
         return
@@ -417,7 +418,7 @@ def main():
     workloads = {}
     if not args.no_workloads:
         for name, fn in (("c1", bench_c1), ("precision", bench_precision), ("batch", bench_batch),
-                         ("learned", bench_learned), ("density", bench_density)):
+                         ("learned", bench_learned), ("density", bench_density), ("layout", bench_layout)):
             t1 = time.perf_counter()
             try:
                 workloads[name] = compact_record(fn(compact_args(args)))
@@ -941,6 +942,80 @@ def bench_c1(args):
     }
     return out
 
+
+
+def bench_layout(args):
+    """Layout-map moves at N=30 (the on-demand swap of the method).  A circuit whose dense 4-qubit
+    blocks alternate between qubits 20..23 (a slow target pattern for the k=4 tile) and 0..3 runs as
+    planned, with the layout swap the cost model inserts (one k_tile_permute sweep), and with the lazy
+    relabel of the MFMA store; the headline plan runs with and without the lazy relabel."""
+    import numpy as np
+    import torch
+
+    import paper_2608_16940_amd as P
+    import workloads as W
+    from paper_2608_16940_amd import costmodel as C
+
+    n = 30
+    reps = 2 if getattr(args, "compact", False) else 5
+    rng = np.random.default_rng(args.seed)
+    gates = []
+    for _ in range(20):
+        gates.append(W.random_dense(n, 4, rng, (20, 21, 22, 23)))
+        gates.append(W.random_dense(n, 4, rng, (0, 1, 2, 3)))
+    params, _ = C.load()
+    base = P.Plan.greedy(n, gates, 4)
+    swp = P.Plan.greedy(n, gates, 4)
+    inserted = swp.add_swaps(params)
+    head = P.Plan.greedy(n, W.headline(n, args.depth, args.seed), args.kmax)
+    sv = P.StateVector(n, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    sync = torch.cuda.synchronize
+
+    def timed(plan, relabel):
+        sv.set_relabel(relabel)
+        sv.reset()
+        plan.run(sv)  # warm
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sv.reset()
+            plan.run(sv)
+        sync()
+        dt = (time.perf_counter() - t0) / reps
+        st = sv.stats()
+        sv.set_relabel(False)
+        return {"ms": dt * 1e3, "relabels": int(st["relabels"]), "permute_sweeps": int(st["permute_sweeps"]),
+                "gate_sweeps": int(st["gate_sweeps"])}
+
+    alt = {"planned": timed(base, False), "model_swap": timed(swp, False), "lazy_relabel": timed(base, True)}
+    hd = {"planned": timed(head, False), "lazy_relabel": timed(head, True)}
+    kernels, _ = timed_run(sv, swp.blocks(), n, stream)
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
+    perm = kernels.get("k_tile_permute (layout swap)")
+    log("bench layout: alternating %.1f / %.1f (swap) / %.1f (relabel) ms; headline %.1f / %.1f (relabel) ms"
+        % (alt["planned"]["ms"], alt["model_swap"]["ms"], alt["lazy_relabel"]["ms"], hd["planned"]["ms"],
+           hd["lazy_relabel"]["ms"]))
+    return {
+        "metric": "layout-map moves: run time with the model's layout swap / lazy relabel vs as planned, N=30 c64",
+        "value": alt["planned"]["ms"] / alt["model_swap"]["ms"], "unit": "x speedup (planned / with swap)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "N=30 complex64: 40 random dense 4-qubit gates alternating between qubits 20..23 "
+                               "and 0..3 (greedy k<=4), and the headline brickwork+QFT plan (greedy k<=%d)"
+                               % args.kmax},
+        "alternating": dict(alt, swaps_inserted=int(inserted)),
+        "headline": hd,
+        "kernels_swap_plan": kernels,
+        "roofline": ({"bound": "hbm", "kernel": "k_tile_permute (layout swap)", "achieved": perm["GBps"],
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": perm["frac"], "avg_ms": perm["avg_ms"],
+                      "launches": perm["launches"]} if perm else None),
+        "summary": {"alternating_ms": {k: v["ms"] for k, v in alt.items()},
+                    "headline_ms": {k: v["ms"] for k, v in hd.items()},
+                    "swaps_inserted": int(inserted),
+                    "headline_relabels": hd["lazy_relabel"]["relabels"]},
+    }
 
 
 def bench_density(args):

@@ -84,6 +84,7 @@ struct TileArgs {
   int64_t goff_i[32];
   int32_t lam_i[32];
   int32_t lamo_i[32];
+  int32_t pswz[7];  // k_tile_permute: LDS swizzle images of local bits 5..11 (lin_swz)
 };
 
 __device__ __forceinline__ int64_t insert_zero_bit(int64_t x, int p) {
@@ -489,9 +490,28 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   }
 }
 
-// In-place bit permutation of the tile's bits in one sweep.
+// LDS address of local index l in the permutation tile: l ^ X(l >> 5), where
+// X is linear over GF(2) (bit 5 + j of l contributes pswz[j] to the low five
+// bits).  The map is a bijection and linear, so the address of a thread's
+// part OR a chunk's part (disjoint bits) is the XOR of the parts' addresses.
+__device__ __forceinline__ int lin_swz(int l, const int32_t *px) {
+  int x = 0;
+#pragma unroll
+  for (int j = 0; j < 7; ++j)
+    if ((l >> (5 + j)) & 1) x ^= px[j];
+  return l ^ x;
+}
+
+// In-place bit permutation of the tile's bits in one sweep.  The tile lands
+// in LDS in tile order and leaves it through the permuted map, so the two
+// phases read LDS along different bits; the host picks X so that the 64
+// lanes of each wave instruction spread over all LDS banks in both phases
+// (without it a wave's reads along high tile bits hit one bank 8 to 64
+// times: one pass ran at 44% of HBM peak).  lam_i / lamo_i hold the chunks'
+// swizzled addresses.
 template <int S>
 __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
+  static_assert(S == 12, "the swizzle covers local bits 5..11");
   constexpr int NT = 256;
   constexpr int CHUNKS = (1 << (S - 1)) / NT;
   __shared__ float2 lds[1 << S];
@@ -505,7 +525,9 @@ __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
       lamo_t |= 1 << a.loc_out[b];
     }
   }
-  const int bout = 1 << a.lb_out;
+  const int wr_t = lin_swz(2 * t, a.pswz);   // identity on load: local index 2t + 512 i
+  const int rd_t = lin_swz(lamo_t, a.pswz);
+  const int rd_b = lin_swz(1 << a.lb_out, a.pswz);
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     int64_t base = tile_of(tile, a.xs);
 #pragma unroll
@@ -515,15 +537,15 @@ __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
     for (int i = 0; i < CHUNKS; ++i) v[i] = ld_stream(a.psi + base + goff_t + a.goff_i[i]);
 #pragma unroll
     for (int i = 0; i < CHUNKS; ++i) {
-      const int l0 = 2 * (i * NT + t);  // identity on load
+      const int l0 = wr_t ^ a.lam_i[i];
       lds[l0] = make_float2(v[i].x, v[i].y);
-      lds[l0 + 1] = make_float2(v[i].z, v[i].w);
+      lds[l0 ^ 1] = make_float2(v[i].z, v[i].w);  // X leaves bit 0 to the pair
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < CHUNKS; ++i) {
-      const int l0 = lamo_t | a.lamo_i[i];
-      st_stream(a.psi + base + goff_t + a.goff_i[i], lds[l0], lds[l0 | bout]);
+      const int l0 = rd_t ^ a.lamo_i[i];
+      st_stream(a.psi + base + goff_t + a.goff_i[i], lds[l0], lds[l0 ^ rd_b]);
     }
     __syncthreads();
   }
@@ -856,6 +878,74 @@ hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi
   }
 }
 
+// GF(2) rank of m vectors of five bits.
+int rank5(const int *v, int m) {
+  int basis[5] = {0, 0, 0, 0, 0}, r = 0;
+  for (int i = 0; i < m; ++i) {
+    int x = v[i] & 31;
+    for (int b = 4; b >= 0 && x; --b) {
+      if (!((x >> b) & 1)) continue;
+      if (!basis[b]) {
+        basis[b] = x;
+        ++r;
+        x = 0;
+      } else {
+        x ^= basis[b];
+      }
+    }
+  }
+  return r;
+}
+
+int lin_swz_host(int l, const int32_t *px) {
+  int x = 0;
+  for (int j = 0; j < 7; ++j)
+    if ((l >> (5 + j)) & 1) x ^= px[j];
+  return l ^ x;
+}
+
+// Swizzle of the permutation tile.  The 64 lanes of a wave instruction vary
+// in six local bits (tile-order bits 1..6: local bits 1..6 on load, their
+// loc_out images on store) and the rest of the address is uniform, so the
+// lanes' 8-byte LDS slots (address mod 32) form an affine image of those six
+// bits: each slot is hit 2^(6 - rank) times.  Rank 5 (two lanes per slot, the
+// minimum for 64 lanes) in both phases is the goal; candidates are the
+// identity, two folds and a fixed pseudo-random sequence, and the first that
+// reaches rank 5 twice is taken (else the best sum).  Bit 0 keeps its value
+// (X acts on bits 5..11 only), so a chunk's two amplitudes stay a pair.
+void choose_perm_swizzle(const TilePlan &tp, int32_t px[7]) {
+  auto score = [&](const int32_t *c) {
+    int w[6], r[6];
+    for (int b = 0; b < 6; ++b) {
+      w[b] = lin_swz_host(1 << (b + 1), c);
+      r[b] = lin_swz_host(1 << tp.loc_out[b + 1], c);
+    }
+    return rank5(w, 6) + rank5(r, 6);
+  };
+  int32_t best[7] = {0, 0, 0, 0, 0, 0, 0};
+  int best_s = score(best);
+  uint32_t lcg = 12345u;
+  for (int cand = 0; cand < 512 && best_s < 10; ++cand) {
+    int32_t c[7];
+    for (int j = 0; j < 7; ++j) {
+      if (cand == 0) {
+        c[j] = 1 << (j % 5);  // fold of bits 5..9 and 10..11 onto 0..4
+      } else if (cand == 1) {
+        c[j] = j < 5 ? 1 << j : 0;
+      } else {
+        lcg = lcg * 1664525u + 1013904223u;
+        c[j] = int32_t((lcg >> 27) & 31);
+      }
+    }
+    const int s = score(c);
+    if (s > best_s) {
+      best_s = s;
+      std::memcpy(best, c, sizeof(best));
+    }
+  }
+  std::memcpy(px, best, sizeof(best));
+}
+
 hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st) {
   constexpr int S = 12;
   if (tp.s != S || tp.n < S) return hipErrorInvalidValue;
@@ -863,6 +953,11 @@ hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st) 
   constexpr int CHUNKS = (1 << (S - 1)) / NT;
   TileArgs a;
   fill_args(tp, NT, CHUNKS, psi, nullptr, &a);
+  choose_perm_swizzle(tp, a.pswz);
+  for (int i = 0; i < CHUNKS; ++i) {
+    a.lam_i[i] = lin_swz_host(a.lam_i[i], a.pswz);
+    a.lamo_i[i] = lin_swz_host(a.lamo_i[i], a.pswz);
+  }
   hipLaunchKernelGGL((k_tile_permute<S>), dim3(grid_of(a.ntiles)), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
