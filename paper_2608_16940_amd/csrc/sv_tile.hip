@@ -43,6 +43,7 @@
 #include <vector>
 
 #include "sv_internal.h"
+#include "sv_swizzle.h"
 
 namespace sv {
 namespace {
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
     for (int i = 0; i < CHUNKS; ++i) {
       const int l0 = wr_t ^ a.lam_i[i];
       lds[l0] = make_float2(v[i].x, v[i].y);
-      lds[l0 ^ 1] = make_float2(v[i].z, v[i].w);  // X leaves bit 0 to the pair
+      lds[l0 ^ 1] = make_float2(v[i].z, v[i].w);  // X reads bits 5..11 only: f(l ^ 1) = f(l) ^ 1
     }
     __syncthreads();
 #pragma unroll
@@ -878,74 +879,6 @@ hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi
   }
 }
 
-// GF(2) rank of m vectors of five bits.
-int rank5(const int *v, int m) {
-  int basis[5] = {0, 0, 0, 0, 0}, r = 0;
-  for (int i = 0; i < m; ++i) {
-    int x = v[i] & 31;
-    for (int b = 4; b >= 0 && x; --b) {
-      if (!((x >> b) & 1)) continue;
-      if (!basis[b]) {
-        basis[b] = x;
-        ++r;
-        x = 0;
-      } else {
-        x ^= basis[b];
-      }
-    }
-  }
-  return r;
-}
-
-int lin_swz_host(int l, const int32_t *px) {
-  int x = 0;
-  for (int j = 0; j < 7; ++j)
-    if ((l >> (5 + j)) & 1) x ^= px[j];
-  return l ^ x;
-}
-
-// Swizzle of the permutation tile.  The 64 lanes of a wave instruction vary
-// in six local bits (tile-order bits 1..6: local bits 1..6 on load, their
-// loc_out images on store) and the rest of the address is uniform, so the
-// lanes' 8-byte LDS slots (address mod 32) form an affine image of those six
-// bits: each slot is hit 2^(6 - rank) times.  Rank 5 (two lanes per slot, the
-// minimum for 64 lanes) in both phases is the goal; candidates are the
-// identity, two folds and a fixed pseudo-random sequence, and the first that
-// reaches rank 5 twice is taken (else the best sum).  Bit 0 keeps its value
-// (X acts on bits 5..11 only), so a chunk's two amplitudes stay a pair.
-void choose_perm_swizzle(const TilePlan &tp, int32_t px[7]) {
-  auto score = [&](const int32_t *c) {
-    int w[6], r[6];
-    for (int b = 0; b < 6; ++b) {
-      w[b] = lin_swz_host(1 << (b + 1), c);
-      r[b] = lin_swz_host(1 << tp.loc_out[b + 1], c);
-    }
-    return rank5(w, 6) + rank5(r, 6);
-  };
-  int32_t best[7] = {0, 0, 0, 0, 0, 0, 0};
-  int best_s = score(best);
-  uint32_t lcg = 12345u;
-  for (int cand = 0; cand < 512 && best_s < 10; ++cand) {
-    int32_t c[7];
-    for (int j = 0; j < 7; ++j) {
-      if (cand == 0) {
-        c[j] = 1 << (j % 5);  // fold of bits 5..9 and 10..11 onto 0..4
-      } else if (cand == 1) {
-        c[j] = j < 5 ? 1 << j : 0;
-      } else {
-        lcg = lcg * 1664525u + 1013904223u;
-        c[j] = int32_t((lcg >> 27) & 31);
-      }
-    }
-    const int s = score(c);
-    if (s > best_s) {
-      best_s = s;
-      std::memcpy(best, c, sizeof(best));
-    }
-  }
-  std::memcpy(px, best, sizeof(best));
-}
-
 hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st) {
   constexpr int S = 12;
   if (tp.s != S || tp.n < S) return hipErrorInvalidValue;
@@ -953,7 +886,7 @@ hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st) 
   constexpr int CHUNKS = (1 << (S - 1)) / NT;
   TileArgs a;
   fill_args(tp, NT, CHUNKS, psi, nullptr, &a);
-  choose_perm_swizzle(tp, a.pswz);
+  choose_perm_swizzle(tp.loc_out, a.pswz);
   for (int i = 0; i < CHUNKS; ++i) {
     a.lam_i[i] = lin_swz_host(a.lam_i[i], a.pswz);
     a.lamo_i[i] = lin_swz_host(a.lamo_i[i], a.pswz);

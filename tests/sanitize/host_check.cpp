@@ -21,6 +21,7 @@
 #include "sv_diagcover.h"
 #include "sv_mlp.h"
 #include "sv_plan.h"
+#include "sv_swizzle.h"
 
 // ------------------------------------------------------------------ stubs
 extern "C" int sv_apply_fused(sv_state *, const double *, const int32_t *, int) { return SV_ERR_UNSUPPORTED; }
@@ -322,12 +323,69 @@ static void mlp_host(Rng &r) {
   CHECK(sv_cost_features(30, 9, t, 0, 1.0, 1, f) == SV_ERR_ARG);
 }
 
+// ------------------------------------------------------------------ permutation-tile swizzle
+// For tile permutations made of up to five disjoint bit exchanges and for
+// arbitrary ones: the chosen map is a bijection of the 2^12 local indices,
+// linear over GF(2), keeps a chunk's two amplitudes (l, l ^ 1) adjacent, and
+// puts the 64 lanes of every wave instruction two to an 8-byte LDS slot in
+// both phases.
+static void perm_swizzle(Rng &r) {
+  for (int trial = 0; trial < 2000; ++trial) {
+    int lo[12];
+    for (int b = 0; b < 12; ++b) lo[b] = b;
+    if (trial % 2) {
+      for (int b = 11; b > 0; --b) {
+        const int j = r.below(b + 1);
+        const int t = lo[b];
+        lo[b] = lo[j];
+        lo[j] = t;
+      }
+    } else {
+      const int np = 1 + r.below(5);
+      for (int e = 0; e < np; ++e) {
+        const int a = r.below(12), b = r.below(12);
+        const int t = lo[a];
+        lo[a] = lo[b];
+        lo[b] = t;
+      }
+    }
+    int32_t px[7];
+    sv::choose_perm_swizzle(lo, px);
+    for (int j = 0; j < 7; ++j) CHECK(px[j] >= 0 && px[j] < 32);
+    if (trial < 50) {
+      std::vector<char> hit(4096, 0);
+      for (int l = 0; l < 4096; ++l) {
+        const int a = sv::lin_swz_host(l, px);
+        CHECK(a >= 0 && a < 4096 && !hit[a] && sv::lin_swz_host(l ^ 1, px) == (a ^ 1));
+        if (a >= 0 && a < 4096) hit[a] = 1;
+      }
+    }
+    for (int t = 0; t < 16; ++t) {
+      const int a = r.below(4096), b = r.below(4096);
+      CHECK(sv::lin_swz_host(a ^ b, px) == (sv::lin_swz_host(a, px) ^ sv::lin_swz_host(b, px)));
+    }
+    // lanes: tile-order bits 1..6; store side through lo[], with a uniform rest
+    const int rest_w = r.below(64) << 7, rest_r = r.below(2);
+    int cw[32] = {0}, cr[32] = {0};
+    for (int lane = 0; lane < 64; ++lane) {
+      int lw = rest_w | (lane << 1), lr = 0;
+      for (int b = 0; b < 6; ++b)
+        if ((lane >> b) & 1) lr |= 1 << lo[b + 1];
+      if (rest_r) lr |= 1 << lo[7];
+      ++cw[sv::lin_swz_host(lw, px) & 31];
+      ++cr[sv::lin_swz_host(lr, px) & 31];
+    }
+    for (int s = 0; s < 32; ++s) CHECK(cw[s] <= 2 && cr[s] <= 2);
+  }
+}
+
 int main() {
   Rng r{20261203};
   planners(r);
   diagonal_cover(r);
   batch_host(r);
   mlp_host(r);
+  perm_swizzle(r);
   if (g_fail) {
     std::fprintf(stderr, "%d checks failed\n", g_fail);
     return 1;
