@@ -218,21 +218,30 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
     const int c = tid / Tc, lt = tid % Tc;
     const int64_t dim = int64_t(1) << n;
     const bool in_lds = int64_t(P) * dim <= kLdsAmps;
-    float2 *st = in_lds ? lds + int64_t(c) * dim : states + I.state_off[c];
+    // the LDS state is addressed through the shared array itself, so that its
+    // accesses compile to LDS instructions (a pointer that may also point to
+    // global memory makes every access a flat one)
+    float2 *const sl = lds + (in_lds ? int64_t(c) * dim : 0);
+    float2 *const sg = states + I.state_off[c];
     const BGate *gl = gates + I.gate_off[c];
     const int my_ng = I.ngc[c];
 
-    for (int64_t x = lt; x < dim; x += Tc) st[x] = make_float2(x == 0 ? 1.f : 0.f, 0.f);
+    if (in_lds) {
+      for (int64_t x = lt; x < dim; x += Tc) sl[x] = make_float2(x == 0 ? 1.f : 0.f, 0.f);
+    } else {
+      for (int64_t x = lt; x < dim; x += Tc) sg[x] = make_float2(x == 0 ? 1.f : 0.f, 0.f);
+    }
     __syncthreads();
     if (in_lds) {
       // lockstep over the pack, one unit (gate or group) per step: a circuit
       // past its last unit only meets the barriers
       int r = 0;  // this circuit's next record
       for (int g = 0; g < ngates; ++g) {
-        if (g < my_ng) r += apply_unit(gl + r, st, int(dim), lt, Tc);
+        if (g < my_ng) r += apply_unit(gl + r, sl, int(dim), lt, Tc);
         __syncthreads();
       }
     } else {
+      float2 *const st = sg;
       // P = 1: the whole workgroup runs the passes of one circuit
       for (int g = 0; g < my_ng;) {
         const BGate M = gl[g];  // pass record
@@ -253,12 +262,12 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
         }
         __syncthreads();
         const int nsl = 1 << (n - kSliceBits);
-        for (int sl = 0; sl < nsl; ++sl) {
+        for (int si = 0; si < nsl; ++si) {
           int64_t base = 0;
           int r = 0;
           for (int q = 0; q < n; ++q) {
             if ((mask >> q) & 1u) continue;
-            if ((sl >> r) & 1) base |= int64_t(1) << q;
+            if ((si >> r) & 1) base |= int64_t(1) << q;
             ++r;
           }
           for (int x = tid; x < kLdsAmps; x += kBT) lds[x] = st[base + offlo[x & 127] + offhi[x >> 7]];
@@ -273,10 +282,10 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
         g += 1 + cnt;
       }
     }
-    // <Z_0> in FP64 over this circuit's slice
+    // <Z_0> in FP64 over this circuit's state
     double s = 0.0;
     for (int64_t x = lt; x < dim; x += Tc) {
-      const float2 a = st[x];
+      const float2 a = in_lds ? sl[x] : sg[x];
       const double pr = double(a.x) * double(a.x) + double(a.y) * double(a.y);
       s += (x & 1) ? -pr : pr;
     }
@@ -287,10 +296,8 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
       __syncthreads();
     }
     if (lt == 0) z0[I.circ[c]] = red[tid];
-    if (in_lds) {
-      float2 *out = states + I.state_off[c];
-      for (int64_t x = lt; x < dim; x += Tc) out[x] = st[x];
-    }
+    if (in_lds)
+      for (int64_t x = lt; x < dim; x += Tc) sg[x] = sl[x];
     __syncthreads();
   }
 }
