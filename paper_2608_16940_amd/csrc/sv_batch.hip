@@ -262,21 +262,46 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
         }
         __syncthreads();
         const int nsl = 1 << (n - kSliceBits);
-        for (int si = 0; si < nsl; ++si) {
-          int64_t base = 0;
+        auto slice_base = [&](int si) {
+          int64_t b = 0;
           int r = 0;
           for (int q = 0; q < n; ++q) {
             if ((mask >> q) & 1u) continue;
-            if ((si >> r) & 1) base |= int64_t(1) << q;
+            if ((si >> r) & 1) b |= int64_t(1) << q;
             ++r;
           }
-          for (int x = tid; x < kLdsAmps; x += kBT) lds[x] = st[base + offlo[x & 127] + offhi[x >> 7]];
-          __syncthreads();
+          return b;
+        };
+        int64_t base = slice_base(0);
+        for (int x = tid; x < kLdsAmps; x += kBT) lds[x] = st[base + offlo[x & 127] + offhi[x >> 7]];
+        __syncthreads();
+        for (int si = 0; si < nsl; ++si) {
           for (int j = 1; j <= cnt;) {
             j += apply_unit(gl + g + j, lds, kLdsAmps, tid, kBT);
             __syncthreads();
           }
-          for (int x = tid; x < kLdsAmps; x += kBT) st[base + offlo[x & 127] + offhi[x >> 7]] = lds[x];
+          // write this slice back and gather the next one in the same sweep:
+          // each thread moves only its own LDS entries, so no barrier is
+          // needed between the two, and the stores overlap the loads
+          if (si + 1 < nsl) {
+            constexpr int PER = kLdsAmps / kBT;
+            const int64_t nbase = slice_base(si + 1);
+            float2 w[PER];  // the next slice's entries of this thread, all loads in flight
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+              const int x = tid + i * kBT;
+              w[i] = st[nbase + offlo[x & 127] + offhi[x >> 7]];
+            }
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+              const int x = tid + i * kBT;
+              st[base + offlo[x & 127] + offhi[x >> 7]] = lds[x];
+              lds[x] = w[i];
+            }
+            base = nbase;
+          } else {
+            for (int x = tid; x < kLdsAmps; x += kBT) st[base + offlo[x & 127] + offhi[x >> 7]] = lds[x];
+          }
           __syncthreads();
         }
         g += 1 + cnt;
