@@ -89,7 +89,7 @@ int sv_batch_prepared_free(sv_batch_prepared *p);
  *                           of following records in the pass; their qubit
  *                           numbers are slice bit positions (rank of the qubit
  *                           in the mask)
- *   kind SV_BATCH_GATE_GROUP q0 = c (2..4): the next c records are
+ *   kind SV_BATCH_GATE_GROUP q0 = c (2..5): the next c records are
  *                           single-qubit gates on distinct qubits that the
  *                           kernel applies in one sweep (runs of consecutive
  *                           single-qubit records, grouped by the host)

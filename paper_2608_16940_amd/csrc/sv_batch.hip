@@ -67,7 +67,7 @@ __device__ __forceinline__ void apply_cnot(const BGate &G, float2 *st, int dim, 
   }
 }
 
-// A group record (kind SV_BATCH_GATE_GROUP, q0 = c in 2..4) is followed by c
+// A group record (kind SV_BATCH_GATE_GROUP, q0 = c in 2..5) is followed by c
 // single-qubit records on distinct qubits.  They commute, so one sweep
 // applies all of them: each thread holds the 2^c amplitudes of a group in
 // registers and applies every 2x2 factor there (one LDS read and write per
@@ -174,7 +174,10 @@ static_assert(kLdsAmps == kBT << 5 && kSliceBits == 14, "linear records assume 2
 
 // One unit at record r (a gate, a group header and its members, or a linear
 // record and its mask record) on an LDS state or slice of dim <= 2^14
-// amplitudes; returns the number of records it spans.
+// amplitudes; returns the number of records it spans.  MAXC: the widest
+// group the caller's records hold (the host groups at most kMaxGroupLds
+// gates for states in LDS and kMaxGroupPass inside passes).
+template <int MAXC>
 __device__ __forceinline__ int apply_unit(const BGate *R, float2 *st, int dim, int lt, int Tc) {
   if (R[0].kind == SV_BATCH_GATE_LINEAR) {
     apply_linear(R, st, lt);  // only in passes: dim = kLdsAmps, Tc = kBT
@@ -184,7 +187,8 @@ __device__ __forceinline__ int apply_unit(const BGate *R, float2 *st, int dim, i
     const int c = R[0].q0;
     if (c == 2) apply_group_c<2>(R + 1, st, dim, lt, Tc);
     else if (c == 3) apply_group_c<3>(R + 1, st, dim, lt, Tc);
-    else apply_group_c<4>(R + 1, st, dim, lt, Tc);
+    else if (MAXC == 4 || c == 4) apply_group_c<4>(R + 1, st, dim, lt, Tc);
+    else apply_group_c<(MAXC > 4 ? 5 : 4)>(R + 1, st, dim, lt, Tc);
     return 1 + c;
   }
   if (R[0].kind == SV_BATCH_GATE_1Q)
@@ -193,6 +197,7 @@ __device__ __forceinline__ int apply_unit(const BGate *R, float2 *st, int dim, i
     apply_cnot(R[0], st, dim, lt, Tc);
   return 1;
 }
+static_assert(kMaxGroupLds == 4 && kMaxGroupPass == 5, "the kernel instantiates groups of 2..5");
 
 __global__ void k_batch_reset(unsigned *counter) {
   if (threadIdx.x == 0) *counter = 0u;
@@ -237,14 +242,20 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
       // past its last unit only meets the barriers
       int r = 0;  // this circuit's next record
       for (int g = 0; g < ngates; ++g) {
-        if (g < my_ng) r += apply_unit(gl + r, sl, int(dim), lt, Tc);
+        if (g < my_ng) r += apply_unit<kMaxGroupLds>(gl + r, sl, int(dim), lt, Tc);
         __syncthreads();
       }
     } else {
       float2 *const st = sg;
+      // P = 1: every thread runs the same circuit, so its records are read
+      // through a wave-uniform pointer (scalar loads, matrices in SGPRs)
+      const uint64_t gp = reinterpret_cast<uint64_t>(gl);
+      const BGate *const glu = reinterpret_cast<const BGate *>(
+          (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(gp >> 32)))) << 32) |
+          uint32_t(__builtin_amdgcn_readfirstlane(int(gp & 0xffffffffu))));
       // P = 1: the whole workgroup runs the passes of one circuit
       for (int g = 0; g < my_ng;) {
-        const BGate M = gl[g];  // pass record
+        const BGate M = glu[g];  // pass record
         const uint32_t mask = uint32_t(M.q0);
         const int cnt = M.q1;
         if (tid < 256) {
@@ -277,7 +288,7 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
         __syncthreads();
         for (int si = 0; si < nsl; ++si) {
           for (int j = 1; j <= cnt;) {
-            j += apply_unit(gl + g + j, lds, kLdsAmps, tid, kBT);
+            j += apply_unit<kMaxGroupPass>(glu + g + j, lds, kLdsAmps, tid, kBT);
             __syncthreads();
           }
           // write this slice back and gather the next one in the same sweep:

@@ -102,17 +102,17 @@ std::vector<BGate> make_passes(const std::vector<BGate> &g, int n) {
   return out;
 }
 
-// Runs of up to four consecutive single-qubit records on distinct qubits
+// Runs of up to maxc consecutive single-qubit records on distinct qubits
 // become one group (a header, then the members).  Within a pass list (after
 // make_passes) only the gates inside each pass are grouped and the pass
 // header's record count follows.
-std::vector<BGate> group_run(const std::vector<BGate> &g, size_t a, size_t b) {
+std::vector<BGate> group_run(const std::vector<BGate> &g, size_t a, size_t b, int maxc) {
   std::vector<BGate> out;
   size_t i = a;
   while (i < b) {
     size_t j = i;
     uint32_t used = 0;
-    while (j < b && j - i < 4 && g[j].kind == SV_BATCH_GATE_1Q && !((used >> g[j].q0) & 1u)) {
+    while (j < b && j - i < size_t(maxc) && g[j].kind == SV_BATCH_GATE_1Q && !((used >> g[j].q0) & 1u)) {
       used |= 1u << g[j].q0;
       ++j;
     }
@@ -171,13 +171,13 @@ std::vector<BGate> merge_cnots(const std::vector<BGate> &g, size_t a, size_t b) 
 }
 
 std::vector<BGate> group_single_qubit(const std::vector<BGate> &g, bool passes) {
-  if (!passes) return group_run(g, 0, g.size());
+  if (!passes) return group_run(g, 0, g.size(), kMaxGroupLds);
   std::vector<BGate> out;
   size_t i = 0;
   while (i < g.size()) {
     const size_t cnt = size_t(g[i].q1);
     std::vector<BGate> merged = merge_cnots(g, i + 1, i + 1 + cnt);
-    std::vector<BGate> body = group_run(merged, 0, merged.size());
+    std::vector<BGate> body = group_run(merged, 0, merged.size(), kMaxGroupPass);
     BGate h = g[i];
     h.q1 = int32_t(body.size());
     out.push_back(h);

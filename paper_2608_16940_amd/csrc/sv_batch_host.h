@@ -16,6 +16,12 @@ namespace batch {
 constexpr int kBT = 512;           // threads per workgroup of the batched kernel
 constexpr int kLdsAmps = 1 << 14;  // 128 KiB of complex64 state slices
 constexpr int kMaxPack = 16;
+// Single-qubit gates applied in one LDS sweep: up to five inside slice
+// passes (2^5 amplitudes per thread, gate records read through a
+// wave-uniform pointer), up to four for states held in LDS, whose
+// per-lane records would not fit the register budget with five.
+constexpr int kMaxGroupPass = 5;
+constexpr int kMaxGroupLds = 4;
 constexpr int kSliceBits = 14;
 constexpr int kGatePass = SV_BATCH_PASS;  // record: q0 = slice qubit mask, q1 = gates in the pass
 
@@ -40,7 +46,7 @@ struct Packed {
 
 // Pass rewriting, grouping and CNOT merging of one circuit's records.
 std::vector<BGate> make_passes(const std::vector<BGate> &g, int n);
-std::vector<BGate> group_run(const std::vector<BGate> &g, size_t a, size_t b);
+std::vector<BGate> group_run(const std::vector<BGate> &g, size_t a, size_t b, int maxc);
 std::vector<BGate> merge_cnots(const std::vector<BGate> &g, size_t a, size_t b);
 std::vector<BGate> group_single_qubit(const std::vector<BGate> &g, bool passes);
 int count_units(const std::vector<BGate> &g);
