@@ -72,10 +72,34 @@ __device__ __forceinline__ void apply_cnot(const BGate &G, float2 *st, int dim, 
 // applies all of them: each thread holds the 2^c amplitudes of a group in
 // registers and applies every 2x2 factor there (one LDS read and write per
 // amplitude instead of c).
+// The 2x2 factors of a group on the 2^C amplitudes a lane holds (element t
+// holds amplitude t ^ r of its group).
 template <int C>
-__device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int dim, int lt, int Tc) {
-  int qs[C], srt[C];
-  int qbit[C];
+__device__ __forceinline__ void group_factors(const BGate *M, int r, float2 *a) {
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const float *m = M[j].m;
+    const bool sw = (r >> j) & 1;  // this lane holds qubit j's pairs swapped
+    const float m0 = sw ? m[6] : m[0], m1 = sw ? m[7] : m[1], m2 = sw ? m[4] : m[2], m3 = sw ? m[5] : m[3];
+    const float m4 = sw ? m[2] : m[4], m5 = sw ? m[3] : m[5], m6 = sw ? m[0] : m[6], m7 = sw ? m[1] : m[7];
+#pragma unroll
+    for (int t = 0; t < (1 << C); ++t) {
+      if ((t >> j) & 1) continue;
+      const float2 x = a[t], y = a[t | (1 << j)];
+      float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
+      o0 = cmad(m0, m1, x, o0);
+      o0 = cmad(m2, m3, y, o0);
+      o1 = cmad(m4, m5, x, o1);
+      o1 = cmad(m6, m7, y, o1);
+      a[t] = o0;
+      a[t | (1 << j)] = o1;
+    }
+  }
+}
+
+// Qubits of a group's members, ascending, and their bits.
+template <int C>
+__device__ __forceinline__ void group_qubits(const BGate *M, int *qs, int *srt, int *qbit) {
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     qs[j] = srt[j] = M[j].q0;
@@ -90,6 +114,12 @@ __device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int di
         srt[j] = srt[j - 1];
         srt[j - 1] = t;
       }
+}
+
+template <int C>
+__device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int dim, int lt, int Tc) {
+  int qs[C], srt[C], qbit[C];
+  group_qubits<C>(M, qs, srt, qbit);
   const int s = rot_shift(srt[0]);
   for (int p = lt; p < (dim >> C); p += Tc) {
     int base = p;
@@ -109,25 +139,7 @@ __device__ __forceinline__ void apply_group_c(const BGate *M, float2 *st, int di
         if ((t >> j) & 1) o |= qbit[j];
       a[t] = st[base + (o ^ orot)];
     }
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const float *m = M[j].m;
-      const bool sw = (r >> j) & 1;  // this lane holds qubit j's pairs swapped
-      const float m0 = sw ? m[6] : m[0], m1 = sw ? m[7] : m[1], m2 = sw ? m[4] : m[2], m3 = sw ? m[5] : m[3];
-      const float m4 = sw ? m[2] : m[4], m5 = sw ? m[3] : m[5], m6 = sw ? m[0] : m[6], m7 = sw ? m[1] : m[7];
-#pragma unroll
-      for (int t = 0; t < (1 << C); ++t) {
-        if ((t >> j) & 1) continue;
-        const float2 x = a[t], y = a[t | (1 << j)];
-        float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
-        o0 = cmad(m0, m1, x, o0);
-        o0 = cmad(m2, m3, y, o0);
-        o1 = cmad(m4, m5, x, o1);
-        o1 = cmad(m6, m7, y, o1);
-        a[t] = o0;
-        a[t | (1 << j)] = o1;
-      }
-    }
+    group_factors<C>(M, r, a);
 #pragma unroll
     for (int t = 0; t < (1 << C); ++t) {
       int o = 0;
@@ -171,6 +183,71 @@ __device__ __forceinline__ void apply_linear(const BGate *R, float2 *lds, int ti
   for (int i = 0; i < PER; ++i) lds[tid + kBT * i] = v[i];
 }
 static_assert(kLdsAmps == kBT << 5 && kSliceBits == 14, "linear records assume 2^14 slices over 512 threads");
+
+// A linear record followed by a five-gate group (the CNOT ladder of one
+// layer, then the next layer's rotations), inside a pass: the group's lane
+// gathers its 32 amplitudes of the mapped slice, old[f(y)], straight from
+// the slice as it was before the linear map, the workgroup meets a barrier,
+// and the lane applies the five factors and writes new[y] in place.  One
+// LDS sweep and one barrier fewer than the two units.  f is linear, and a
+// group position y = base ^ o (o a combination of the group's qubit bits)
+// maps to f(base) ^ f(o), so f(o) is the XOR of the masks of o's bits.
+// Passes hold kLdsAmps = 2^14 amplitudes over kBT = 512 threads: 2^14 / 2^5
+// groups, one per thread, so every thread meets the barrier once.
+__device__ __forceinline__ void apply_linear_group5(const BGate *RL, const BGate *M, float2 *lds, int tid) {
+  constexpr int C = 5;
+  static_assert((kLdsAmps >> C) == kBT, "one five-qubit group per thread of a pass");
+  int32_t mk[kSliceBits];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) mk[b] = __float_as_int(RL[0].m[b]);
+#pragma unroll
+  for (int b = 8; b < kSliceBits; ++b) mk[b] = __float_as_int(RL[1].m[b - 8]);
+  auto fmap = [&](int y) {
+    int32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < kSliceBits; ++b)
+      if ((y >> b) & 1) v ^= mk[b];
+    return v;
+  };
+  int qs[C], srt[C], qbit[C];
+  group_qubits<C>(M, qs, srt, qbit);
+  const int s = rot_shift(srt[0]);
+  const int p = tid;
+  int base = p;
+#pragma unroll
+  for (int j = 0; j < C; ++j) base = ins0(base, srt[j]);
+  const int r = (p >> s) & ((1 << C) - 1);  // element t holds amplitude t ^ r
+  int orot = 0, forot = 0;
+  int32_t fq[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    fq[j] = mk[qs[j]];  // f of qubit j's bit
+    if ((r >> j) & 1) {
+      orot |= qbit[j];
+      forot ^= fq[j];
+    }
+  }
+  const int32_t fb = fmap(base) ^ forot;
+  float2 a[1 << C];
+#pragma unroll
+  for (int t = 0; t < (1 << C); ++t) {
+    int32_t fo = fb;
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if ((t >> j) & 1) fo ^= fq[j];
+    a[t] = lds[fo];
+  }
+  __syncthreads();  // every lane has gathered before any position is overwritten
+  group_factors<C>(M, r, a);
+#pragma unroll
+  for (int t = 0; t < (1 << C); ++t) {
+    int o = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if ((t >> j) & 1) o |= qbit[j];
+    lds[base + (o ^ orot)] = a[t];
+  }
+}
 
 // One unit at record r (a gate, a group header and its members, or a linear
 // record and its mask record) on an LDS state or slice of dim <= 2^14
@@ -288,7 +365,14 @@ __global__ __launch_bounds__(kBT) void k_batch(const BItem *__restrict__ items, 
         __syncthreads();
         for (int si = 0; si < nsl; ++si) {
           for (int j = 1; j <= cnt;) {
-            j += apply_unit<kMaxGroupPass>(glu + g + j, lds, kLdsAmps, tid, kBT);
+            const BGate *R = glu + g + j;
+            if (R[0].kind == SV_BATCH_GATE_LINEAR && j + 2 <= cnt && R[2].kind == SV_BATCH_GATE_GROUP &&
+                R[2].q0 == 5) {
+              apply_linear_group5(R, R + 3, lds, tid);  // its members follow the header inside the pass
+              j += 2 + 1 + 5;
+            } else {
+              j += apply_unit<kMaxGroupPass>(R, lds, kLdsAmps, tid, kBT);
+            }
             __syncthreads();
           }
           // write this slice back and gather the next one in the same sweep:
