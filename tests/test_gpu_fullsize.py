@@ -77,6 +77,9 @@ def test_headline_n30_against_oracle_samples(P):
     rel = float(np.sqrt(np.sum(d ** 2) / np.sum(np.abs(ref) ** 2)))
     say("headline n30: max|d| %.3e  rel_l2(sample) %.3e  typical |amp| %.3e" % (d.max(), rel, np.abs(ref).mean()))
     assert d.max() <= 1e-5
+    # the absolute bar says little for amplitudes of size ~3e-5: every sampled
+    # amplitude is also held to 1e-5 of the largest one (measured ~1e-6)
+    assert d.max() <= 1e-5 * np.abs(ref).max()
     assert rel <= 1e-5
     nrm = sv.norm()
     assert abs(nrm - 1) <= 1e-5
