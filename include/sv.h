@@ -235,7 +235,7 @@ const char *sv_last_error(void);
  * tile-index bits x..x+2, so each XCD walks runs of 2^x consecutive tiles
  * (states with fewer than 2^(x+3) tiles keep the plain order).  0 = plain
  * order (workgroup i takes tile i); -1 (default) = the order measured
- * fastest on MI355X. */
+ * fastest on MI355X: plain for gate sweeps, x = 9 for layout permutations. */
 #define SV_OPT_TILE_ORDER 8
 
 int sv_set_option(sv_state *s, int key, int value);

@@ -138,8 +138,10 @@ int sv_plan_block_matrix(const sv_plan *p, int i, double *out);
  * predicts, with the model, the time the next `horizon` blocks gain at their
  * new physical positions.  It inserts the best move as a layout-swap block
  * when that gain exceeds the predicted cost of the permutation sweeps
- * (ceil(exchanges / 5) in-place tile passes, each priced as a streaming
- * sweep times SV_PLAN_SWAP_SWEEP_FACTOR) by more than the factor
+ * (the in-place tile passes sv_permute_layout runs for the move: up to five
+ * disjoint exchanges per pass while the tile keeps physical bits 0..3; each
+ * priced as a streaming sweep times SV_PLAN_SWAP_SWEEP_FACTOR) by more than
+ * the factor
  * (1 + margin).  A swap block changes only where qubits are stored, never
  * the logical state.  States under SV_PLAN_SWAP_MIN_QUBITS qubits get no
  * swaps: the model was trained from 24 qubits up, and smaller states stay in

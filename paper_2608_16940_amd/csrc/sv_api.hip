@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "sv_diagcover.h"
+#include "sv_permute_host.h"
 #include "sv_internal.h"
 #include "sv_plan.h"
 
@@ -553,35 +554,15 @@ int sv_permute_layout(sv_state *s, const int32_t *new_layout) {
       }
       seen[p] = true;
     }
-    // Selection order: fill physical positions 0..n-1 with their final qubits,
-    // one bit transposition at a time (Lemma 2: each exchange updates
-    // L = tau o L).  Consecutive disjoint transpositions commute, so several
-    // of them run as one in-place tile pass (one sweep) when the state has at
-    // least 12 qubits (five pairs at most, so that the tile always keeps physical
-    // bit 0); smaller states use single transposition passes.
-    int32_t L[64], Linv[64];
-    for (int q = 0; q < n; ++q) {
-      L[q] = s->L[q];
-      Linv[s->L[q]] = q;
-    }
-    std::vector<std::pair<int, int>> swaps;
-    for (int p = 0; p < n; ++p) {
-      int want = -1;
-      for (int q = 0; q < n; ++q)
-        if (new_layout[q] == p) want = q;
-      const int cur = L[want];
-      if (cur == p) continue;
-      swaps.push_back({p, cur});
-      const int a = Linv[p], b = Linv[cur];
-      L[a] = cur;
-      L[b] = p;
-      Linv[p] = b;
-      Linv[cur] = a;
-    }
-    constexpr int kTileBits = 12;
+    // Selection order (permutation_swaps): fill physical positions 0..n-1
+    // with their final qubits, one bit transposition at a time.  Consecutive
+    // disjoint transpositions commute, so several of them run as one
+    // in-place tile pass (permutation_pass_end) when the state has at least
+    // kPermTileBits qubits; smaller states use single transposition passes.
+    const std::vector<std::pair<int, int>> swaps = permutation_swaps(s->L, new_layout, n);
     size_t i = 0;
     while (i < swaps.size()) {
-      if (n < kTileBits) {
+      if (n < kPermTileBits) {
         SV_HIP_CHECK(launch_swap_bits(s->amps, n, swaps[i].first, swaps[i].second, s->st));
         swap_physical(s, swaps[i].first, swaps[i].second);
         s->stats.swap_half_sweeps += 1;
@@ -589,20 +570,15 @@ int sv_permute_layout(sv_state *s, const int32_t *new_layout) {
         ++i;
         continue;
       }
+      const size_t j = permutation_pass_end(swaps, i);
       uint64_t used = 0;
-      size_t j = i;
-      while (j < swaps.size() && j - i < 5) {
-        const uint64_t m = (uint64_t(1) << swaps[j].first) | (uint64_t(1) << swaps[j].second);
-        if (used & m) break;
-        used |= m;
-        ++j;
-      }
-      // tile: the exchanged bits plus the lowest other bits, 12 in total
+      for (size_t t = i; t < j; ++t) used |= (uint64_t(1) << swaps[t].first) | (uint64_t(1) << swaps[t].second);
+      // tile: the exchanged bits plus the lowest other bits, kPermTileBits in all
       uint64_t smask = used;
-      for (int p = 0; p < n && __builtin_popcountll(smask) < kTileBits; ++p) smask |= uint64_t(1) << p;
+      for (int p = 0; p < n && __builtin_popcountll(smask) < kPermTileBits; ++p) smask |= uint64_t(1) << p;
       TilePlan tp;
       tp.n = n;
-      tp.s = kTileBits;
+      tp.s = kPermTileBits;
       tp.order = s->tile_order;
       int b = 0;
       for (int p = 0; p < n; ++p)

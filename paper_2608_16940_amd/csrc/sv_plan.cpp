@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "sv_diagcover.h"
+#include "sv_permute_host.h"
 #include "sv_guard.h"
 #include "sv_mlp.h"
 
@@ -892,7 +893,9 @@ extern "C" int sv_plan_swaps(sv_plan *p, const float *mlp_params, int mlp_nin, i
             }
             if (!c.diag) gain += cost(c, La) - cost(c, Lb);
           }
-          const double price = double((moves + 4) / 5) * stream * SV_PLAN_SWAP_SWEEP_FACTOR;
+          // the tile passes sv_permute_layout will run for this move
+          const double price =
+              double(sv::permutation_passes(L.data(), L2.data(), n)) * stream * SV_PLAN_SWAP_SWEEP_FACTOR;
           if (gain > price * (1.0 + margin) && gain - price > best) {
             best = gain - price;
             bestL = std::move(L2);

@@ -43,7 +43,7 @@
 #include <vector>
 
 #include "sv_internal.h"
-#include "sv_swizzle.h"
+#include "sv_permute_host.h"
 
 namespace sv {
 namespace {
@@ -512,7 +512,7 @@ __device__ __forceinline__ int lin_swz(int l, const int32_t *px) {
 // swizzled addresses.
 template <int S>
 __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
-  static_assert(S == 12, "the swizzle covers local bits 5..11");
+  static_assert(S == 12, "the swizzle covers local bits 5..11");  // kPermTileBits
   constexpr int NT = 256;
   constexpr int CHUNKS = (1 << (S - 1)) / NT;
   __shared__ float2 lds[1 << S];
@@ -879,11 +879,19 @@ hipError_t launch_tile_mfma(const TilePlan &tp, int prec, int opsrc, float2 *psi
   }
 }
 
-hipError_t launch_tile_permute(const TilePlan &tp, float2 *psi, hipStream_t st) {
-  constexpr int S = 12;
-  if (tp.s != S || tp.n < S) return hipErrorInvalidValue;
+// Default workgroup-to-tile order of layout permutations: the XCD bits on
+// tile-index bits 9..11.  Measured at N=30 over 36 exchange patterns: 159 ms
+// in all against 183 ms in the plain order, faster on 26 of them (exchanging
+// bits 20..23 with 0..3: 4.8 -> 2.9 ms).
+constexpr int kPermuteTileOrder = 9;
+
+hipError_t launch_tile_permute(const TilePlan &tp_in, float2 *psi, hipStream_t st) {
+  constexpr int S = kPermTileBits;
+  if (tp_in.s != S || tp_in.n < S) return hipErrorInvalidValue;
   constexpr int NT = 256;
   constexpr int CHUNKS = (1 << (S - 1)) / NT;
+  TilePlan tp = tp_in;
+  if (tp.order < 0) tp.order = kPermuteTileOrder;
   TileArgs a;
   fill_args(tp, NT, CHUNKS, psi, nullptr, &a);
   choose_perm_swizzle(tp.loc_out, a.pswz);

@@ -21,7 +21,7 @@
 #include "sv_diagcover.h"
 #include "sv_mlp.h"
 #include "sv_plan.h"
-#include "sv_swizzle.h"
+#include "sv_permute_host.h"
 
 // ------------------------------------------------------------------ stubs
 extern "C" int sv_apply_fused(sv_state *, const double *, const int32_t *, int) { return SV_ERR_UNSUPPORTED; }
@@ -379,6 +379,54 @@ static void perm_swizzle(Rng &r) {
   }
 }
 
+// ------------------------------------------------------------------ permutation passes
+// Random layouts of 12..30 qubits: the exchanges take L to the target, each
+// pass holds disjoint exchanges, at most five, and a tile of 12 bits that
+// keeps physical bits 0..3; the pass count matches.
+static void perm_passes(Rng &r) {
+  for (int trial = 0; trial < 500; ++trial) {
+    const int n = 12 + r.below(19);
+    int32_t L[64], T[64];
+    for (int q = 0; q < n; ++q) L[q] = T[q] = q;
+    for (int q = n - 1; q > 0; --q) {
+      int j = r.below(q + 1), t = L[q];
+      L[q] = L[j];
+      L[j] = t;
+      j = r.below(q + 1);
+      t = T[q];
+      T[q] = T[j];
+      T[j] = t;
+    }
+    const std::vector<std::pair<int, int>> sw = sv::permutation_swaps(L, T, n);
+    int32_t cur[64], inv[64];
+    for (int q = 0; q < n; ++q) {
+      cur[q] = L[q];
+      inv[L[q]] = q;
+    }
+    int passes = 0;
+    for (size_t i = 0; i < sw.size();) {
+      const size_t j = sv::permutation_pass_end(sw, i);
+      CHECK(j > i && j - i <= size_t(sv::kPermMaxPairs));
+      uint64_t used = 0;
+      for (size_t t = i; t < j; ++t) {
+        const uint64_t m = (uint64_t(1) << sw[t].first) | (uint64_t(1) << sw[t].second);
+        CHECK(!(used & m));
+        used |= m;
+        const int a = inv[sw[t].first], b = inv[sw[t].second];
+        cur[a] = sw[t].second;
+        cur[b] = sw[t].first;
+        inv[sw[t].first] = b;
+        inv[sw[t].second] = a;
+      }
+      CHECK(j - i == 1 || __builtin_popcountll(used | sv::kPermLowRun) <= sv::kPermTileBits);
+      ++passes;
+      i = j;
+    }
+    for (int q = 0; q < n; ++q) CHECK(cur[q] == T[q]);
+    CHECK(passes == sv::permutation_passes(L, T, n));
+  }
+}
+
 int main() {
   Rng r{20261203};
   planners(r);
@@ -386,6 +434,7 @@ int main() {
   batch_host(r);
   mlp_host(r);
   perm_swizzle(r);
+  perm_passes(r);
   if (g_fail) {
     std::fprintf(stderr, "%d checks failed\n", g_fail);
     return 1;

@@ -4,8 +4,9 @@ tests/sanitize/host_check.cpp drives the fusion planners (every score, the
 cap search, repeated rounds, the layout-swap pass), the diagonal cover (also
 that it allocates nothing after a thread's first call), the batched path's
 host pass with its threaded packing, the host MLP forward on seeded
-random inputs and bad arguments, and the LDS swizzle chosen for layout
-permutation tiles (bijective, linear, two lanes per bank slot).  It is built with g++ together with the
+random inputs and bad arguments, and the layout permutations' host side
+(exchange lists and their tile passes; the LDS swizzle of a pass:
+bijective, linear, two lanes per bank slot).  It is built with g++ together with the
 library's host-only sources, once with AddressSanitizer and
 UndefinedBehaviorSanitizer and once with ThreadSanitizer; a sanitizer report
 or a failed check fails the test.
