@@ -168,7 +168,22 @@ __global__ __launch_bounds__(kThreads) void k_1q_shuffle(float4 *__restrict__ ps
 // its chunk-bit position (lowest first); with f fixed bits the pass reads and
 // writes 2^-f of the state.  The host covers the entries that are not 1 with
 // a few such subcubes, one launch each.
+//
+// Fixed bits low in the address (physical 4..13) narrow the set of HBM
+// channels that the workgroups in flight at one time reach: at N=30, 32 and
+// 34 a sixteenth of the state with physical bits 6..9 fixed streamed at
+// 3.8-4.3 TB/s against 6.2-6.4 with bits 20..23 fixed.  Such sweeps exchange
+// work index bits 14..18 (the 2^14-chunk block index, above what
+// stream_chunk permutes) with the five work bits that land at physical bits
+// 25..29, so consecutive blocks sit 32 MiB apart.  Over the sets of three to
+// five fixed bits in 4..13 measured at those sizes the rate went from
+// 3.6-5.6 to 4.6-6.3 TB/s, and no set lost more than 3%.  With one or two
+// fixed bits, or fixed bits higher up, the plain order was as fast or faster
+// (the exchange with bits 21..24 fixed: 3.5-4.2 TB/s), so the host asks for
+// it only for the low sets.
 constexpr int kDiagByValue = 16;  // tables up to k = 4 travel in the kernel arguments
+constexpr int kDiagXchgLo = 14;   // lowest work bit of the exchanged block-index field
+constexpr int kDiagXchgBits = 5;
 struct DiagArgs {
   int k;
   int tgt[8];  // physical position of block bit j
@@ -176,6 +191,7 @@ struct DiagArgs {
   int nfix;    // bits held fixed by this partial sweep
   int fix[8];  // their chunk-bit positions (physical position - 1), ascending
   int fixval;  // bit i: the value of fix[i]
+  int xhi;     // work bit where the field exchanged with bits 14..18 starts (0: no exchange)
   float2 small[kDiagByValue];  // the table when dtab is null
 };
 
@@ -184,8 +200,15 @@ __device__ __forceinline__ int64_t insert_bit(int64_t x, int p, int64_t v) {
   return ((x >> p) << (p + 1)) | (v << p) | low;
 }
 
+// Exchange of the disjoint bit fields [kDiagXchgLo, +5) and [hi, +5) of x.
+__device__ __forceinline__ int64_t xchg_fields(int64_t x, int hi) {
+  const int64_t m = (int64_t(1) << kDiagXchgBits) - 1;
+  const int64_t lo = (x >> kDiagXchgLo) & m, up = (x >> hi) & m;
+  return (x & ~((m << kDiagXchgLo) | (m << hi))) | (up << kDiagXchgLo) | (lo << hi);
+}
+
 // nwork = chunks visited: 2^(N-1) >> nfix.
-template <int UNR>
+template <int UNR, bool XCHG>
 __global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, int64_t nwork,
                                                    const float2 *__restrict__ dtab, DiagArgs a) {
   __shared__ float2 tab[256];
@@ -200,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(float4 *__restrict__ psi4, in
       const int64_t lin = c0 + int64_t(u) * kThreads;
       cc[u] = -1;
       if (lin < nwork) {
-        int64_t c = stream_chunk(lin, nwork);
+        int64_t c = stream_chunk(XCHG ? xchg_fields(lin, a.xhi) : lin, nwork);
         for (int i = 0; i < a.nfix; ++i) c = insert_bit(c, a.fix[i], (a.fixval >> i) & 1);
         cc[u] = c;
         v[u] = __builtin_nontemporal_load(reinterpret_cast<const floatx4 *>(psi4 + c));
@@ -665,10 +688,20 @@ hipError_t launch_diag(float2 *psi, int n, int k, const int32_t *A, const float2
     a.fix[i] = fx[i].first;
     a.fixval |= fx[i].second << i;
   }
+  // three to five fixed bits, all at physical 13 or below, on states of 2^30
+  // amplitudes or more: the fields [14, 19) and [24 - nfix, 29 - nfix) of the
+  // work index are disjoint and inside its n - 1 - nfix bits, and the upper
+  // one lands at physical bits 25..29 (every fixed bit sits below it)
+  a.xhi = 0;
+  if (n >= 30 && nfix >= 3 && nfix <= 5 && fx[nfix - 1].first <= 12) a.xhi = 24 - nfix;
   constexpr int UNR = 1;
   const int64_t nwork = (int64_t(1) << (n - 1)) >> nfix;
-  hipLaunchKernelGGL(k_diag<UNR>, dim3(grid_for(nwork, kThreads * UNR, kFullGrid)), dim3(kThreads), 0, st,
-                     reinterpret_cast<float4 *>(psi), nwork, d_dev, a);
+  if (a.xhi)
+    hipLaunchKernelGGL((k_diag<UNR, true>), dim3(grid_for(nwork, kThreads * UNR, kFullGrid)), dim3(kThreads), 0, st,
+                       reinterpret_cast<float4 *>(psi), nwork, d_dev, a);
+  else
+    hipLaunchKernelGGL((k_diag<UNR, false>), dim3(grid_for(nwork, kThreads * UNR, kFullGrid)), dim3(kThreads), 0,
+                       st, reinterpret_cast<float4 *>(psi), nwork, d_dev, a);
   return hipGetLastError();
 }
 

@@ -118,3 +118,58 @@ def test_partial_diagonals_in_bound_plan_and_graph(P):
         np.testing.assert_array_equal(sv.physical_state(), eager, err_msg="graph replay %d" % rep)
     bound.close()
     sv.close()
+
+
+# At 2^30 amplitudes and more, sweeps with three to five fixed bits all at
+# physical 13 or below walk their subcube in a different order (two fields of
+# the work index exchanged); the others keep the plain order.
+LARGE = [
+    ((6, 7, 8, 9), lambda rng: controlled_table(4, [0, 1, 2, 3], rng), 1 / 16),   # exchanged order
+    ((9, 7, 8), lambda rng: controlled_table(3, [0, 1, 2], rng), 1 / 8),          # exchanged order
+    ((5, 9, 12, 13), lambda rng: cz_pair_table(), 6 / 16),                        # four subcubes, 3-4 fixed bits
+    ((4, 5, 6, 7, 8), lambda rng: controlled_table(5, [0, 1, 2, 3, 4], rng), 1 / 32),  # five fixed bits
+    ((20, 21, 22, 23), lambda rng: controlled_table(4, [0, 1, 2, 3], rng), 1 / 16),    # plain order
+    ((8, 9), lambda rng: controlled_table(2, [0, 1], rng), 1 / 4),                # plain order (two bits)
+]
+
+
+@pytest.mark.parametrize("targets,table,frac", LARGE)
+def test_partial_diagonal_2e30(P, targets, table, frac):
+    """N=30: every amplitude of the subcube is multiplied by its entry exactly once (a traversal that
+    visited a chunk twice or skipped one would fail), every other amplitude is bit-for-bit unchanged.
+    Checked on the device in slices against torch's complex64 product of the saved state."""
+    import torch
+    n = 30
+    rng = np.random.default_rng(sum(targets))
+    d = table(rng)
+    sv = P.StateVector(n)
+    sv.set_relabel(False)
+    for q in range(n):  # a product state whose amplitudes are all different from zero
+        a, b = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        nr = np.sqrt(abs(a) ** 2 + abs(b) ** 2)
+        a, b = a / nr, b / nr
+        sv.apply(np.array([[a, -np.conj(b)], [b, np.conj(a)]]), (q,))
+    assert list(sv.layout()) == list(range(n))
+    before = sv.amps.clone()
+    st0 = sv.stats()
+    sv.apply(np.diag(d), targets)
+    st1 = sv.stats()
+    assert st1["diag_chunks"] - st0["diag_chunks"] == round(frac * (1 << (n - 1)))
+    dev = sv.amps.device
+    dt = torch.tensor(d.astype(np.complex64), device=dev)
+    step = 1 << 26
+    for s0 in range(0, 1 << n, step):
+        idx = torch.arange(s0, s0 + step, device=dev, dtype=torch.int64)
+        r = torch.zeros_like(idx)
+        for j, t in enumerate(targets):
+            r |= ((idx >> t) & 1) << j
+        f = dt[r]
+        b = before[s0:s0 + step]
+        a = sv.amps[s0:s0 + step]
+        one = f == 1
+        assert torch.equal(a[one], b[one]), s0
+        e = (a[~one] - b[~one] * f[~one]).abs()
+        bound = 1e-6 * b[~one].abs() + 1e-12
+        assert bool((e <= bound).all()), (s0, float(e.max()))
+        assert int((~one).sum()) == int(round(frac * step)), s0
+    sv.close()
