@@ -146,13 +146,24 @@ struct Scheme {
   static constexpr int bytes = (alg == ALG_GAUSS_F32 || alg == ALG_CPLX_BF16X3) ? (1 << (2 * K + 3)) : (1 << (2 * K + 4));
 };
 
+// Reduction split: at k = 7 with the operand in LDS (128 KiB: one workgroup
+// per CU) eight waves work on a tile, two per output tile, each over half of
+// the reduction; the two partial sums meet in LDS (upper half first, then the
+// lower half adds its own), so the matrix cores have two waves per SIMD to
+// draw from instead of one.
+template <int K, int PREC, int OPS>
+struct KSplit {
+  static constexpr int value = (K == 7 && OPS == OP_LDS) ? 2 : 1;
+};
+
 // Occupancy target (waves per SIMD the register budget is cut for).  FP32
 // k=5 with the operand in LDS fits four 40 KiB workgroups per CU in 125
 // VGPRs; the other k=5 forms would spill at that budget and keep three.
 template <int K, int PREC, int OPS>
 struct WavesPerSimd {
   static constexpr int value =
-      K <= 4 ? 4 : (K == 5 ? ((PREC == SV_PREC_FP32 && OPS == OP_LDS) ? 4 : 3) : ((K == 7 && OPS == OP_LDS) ? 1 : 2));
+      K <= 4 ? 4 : (K == 5 ? ((PREC == SV_PREC_FP32 && OPS == OP_LDS) ? 4 : 3) : ((K == 7 && OPS == OP_LDS) ? 1 : 2)) *
+                       KSplit<K, PREC, OPS>::value;
 };
 
 // Register prefetch of the next tile: measured at N=30 on MI355X, FP32 k=6
@@ -166,8 +177,11 @@ struct Prefetch {
 constexpr int kPrefetchGridPerCU = 16;
 
 template <int K, int M, int PREC, int OPS>
-__global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_tile_mfma(TileArgs a) {
-  constexpr int NT = 256;               // four waves for every gate width
+__global__ __launch_bounds__((256 * KSplit<K, PREC, OPS>::value), (WavesPerSimd<K, PREC, OPS>::value)) void k_tile_mfma(
+    TileArgs a) {
+  constexpr int KSP = KSplit<K, PREC, OPS>::value;
+  constexpr int NT = 256 * KSP;         // four waves per reduction part
+  constexpr int TB = (KSP == 2) ? 9 : 8;  // thread bits: tile-order bits 1..TB
   constexpr int S = K + M;
   constexpr int TILE = 1 << S;
   constexpr int CHUNKS = TILE / 2 / NT;  // 16-byte chunks per thread per tile
@@ -202,7 +216,7 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   int64_t goff_t = 0;
   int lam_t = 0, lamo_t = 0;
 #pragma unroll
-  for (int b = 1; b <= 8; ++b) {
+  for (int b = 1; b <= TB; ++b) {
     if ((t >> (b - 1)) & 1) {
       goff_t |= int64_t(1) << a.sbit[b];
       lam_t |= 1 << a.loc_in[b];
@@ -211,9 +225,10 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
   }
   const int bin = 1 << a.lb_in, bout = 1 << a.lb_out;
 
-  // wave -> column block and its output tiles mt0 + j * (4 / NCB)
-  const int cb = wave % NCB;
-  const int mt0 = wave / NCB;
+  // wave -> reduction part, column block and its output tiles mt0 + j * (4 / NCB)
+  const int ks = wave >> 2;
+  const int cb = (wave & 3) % NCB;
+  const int mt0 = (wave & 3) / NCB;
   constexpr int MT_STEP = 4 / NCB;
 
   // ---- operand
@@ -319,9 +334,11 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
       // rolled (5-7% faster than 8 steps at every target pattern), k = 6 and 7
       // with the operand in LDS fully unrolled (9% and 15% faster); the
       // cache-operand forms would spill fully unrolled and keep 8 steps
-      constexpr int UNR = (K == 5) ? 1 : (OPS == OP_LDS ? AH : 8);
+      constexpr int AHP = AH / KSP;  // steps of one reduction part
+      constexpr int UNR = (K == 5) ? 1 : (OPS == OP_LDS ? AHP : 8);
 #pragma unroll UNR
-      for (int kk = 0; kk < AH; ++kk) {
+      for (int k2 = 0; k2 < AHP; ++k2) {
+        const int kk = ks * AHP + k2;
         const float2 x = lds[swz<K>(gbase | (h * AH + kk))];
         const float xs = x.x + x.y;
 #pragma unroll
@@ -336,16 +353,31 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
         }
       }
       if constexpr (SHARED_GROUPS) __syncthreads();  // sibling waves finished reading these groups
+      // a split reduction: the upper part stores its partial sums, the lower part adds its own
 #pragma unroll
-      for (int j = 0; j < MPW; ++j) {
-        const int mt = mt0 + j * MT_STEP;
+      for (int part = KSP - 1; part >= 0; --part) {
+        if (part < KSP - 1) __syncthreads();
+        if (ks == part) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float t1 = acc[j][r], t2 = acc[MPW + j][r], t3 = acc[2 * MPW + j][r];
-          lds[swz<K>(gbase | (h * AH + 16 * mt + r))] = make_float2(t1 - t2, t3 - t1 - t2);
+          for (int j = 0; j < MPW; ++j) {
+            const int mt = mt0 + j * MT_STEP;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float t1 = acc[j][r], t2 = acc[MPW + j][r], t3 = acc[2 * MPW + j][r];
+              float2 y = make_float2(t1 - t2, t3 - t1 - t2);
+              const int ix = swz<K>(gbase | (h * AH + 16 * mt + r));
+              if (part < KSP - 1) {
+                const float2 q = lds[ix];
+                y.x += q.x;
+                y.y += q.y;
+              }
+              lds[ix] = y;
+            }
+          }
         }
       }
     } else if constexpr (ALG == ALG_EMBED_F32) {
+      static_assert(KSP == 1, "the embedding forms (k = 4) keep one reduction part");
       // step kk uses real (HALF h + kk) of this lane's group
 #pragma unroll
       for (int kk = 0; kk < HALF; ++kk) {
@@ -366,6 +398,7 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
           lds[swz<K>(gbase | (h * AH + 8 * mt + e))] = make_float2(acc[j][2 * e], acc[j][2 * e + 1]);
       }
     } else if constexpr (ALG == ALG_EMBED_BF16X3) {
+      static_assert(KSP == 1, "the embedding forms (k = 4) keep one reduction part");
       // k = 4 only (the complex form takes k >= 5)
       const shortx4 *oph = reinterpret_cast<const shortx4 *>(opsrc);
 #pragma unroll
@@ -416,7 +449,8 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
       // lane's group; operand unit ((P MTT + mt) KS + kk) holds plane P in
       // (Gr hi, Gr lo, Gi hi, Gi lo) for those eight columns
       constexpr int KS = AH / 8;
-      constexpr int UNR = (OPS == OP_LDS && K >= 6) ? KS : (K == 5 ? 1 : 2);  // wider unrolls spill
+      constexpr int KSS = KS / KSP;  // steps of one reduction part
+      constexpr int UNR = (OPS == OP_LDS && K >= 6) ? KSS : (K == 5 ? 1 : 2);  // wider unrolls spill
       constexpr int XS = (BSETS - 1) * MPW;  // cross-term accumulator offset
       floatx16 *accR = acc, *accI = acc + BSETS * MPW;
       const uint2 *ldsu = reinterpret_cast<const uint2 *>(lds);
@@ -428,7 +462,8 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
           return reinterpret_cast<const uint4 *>(opsrc)[q * 64 + lane];
       };
 #pragma unroll UNR
-      for (int kk = 0; kk < KS; ++kk) {
+      for (int k2 = 0; k2 < KSS; ++k2) {
+        const int kk = ks * KSS + k2;
         uint2 sl[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) sl[e] = ldsu[swz<K>(gbase | (h * AH + 8 * kk + e))];
@@ -465,17 +500,30 @@ __global__ __launch_bounds__(256, (WavesPerSimd<K, PREC, OPS>::value)) void k_ti
         }
       }
       if constexpr (SHARED_GROUPS) __syncthreads();
+      // a split reduction: the upper part stores its partial sums, the lower part adds its own
 #pragma unroll
-      for (int j = 0; j < MPW; ++j) {
-        const int mt = mt0 + j * MT_STEP;
+      for (int part = KSP - 1; part >= 0; --part) {
+        if (part < KSP - 1) __syncthreads();
+        if (ks == part) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float re = accR[j][r], im = accI[j][r];
-          if constexpr (BSETS > 1) {
-            re += accR[XS + j][r];
-            im += accI[XS + j][r];
+          for (int j = 0; j < MPW; ++j) {
+            const int mt = mt0 + j * MT_STEP;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              float re = accR[j][r], im = accI[j][r];
+              if constexpr (BSETS > 1) {
+                re += accR[XS + j][r];
+                im += accI[XS + j][r];
+              }
+              const int ix = swz<K>(gbase | (h * AH + 16 * mt + r));
+              if (part < KSP - 1) {
+                const float2 q = lds[ix];
+                re += q.x;
+                im += q.y;
+              }
+              lds[ix] = make_float2(re, im);
+            }
           }
-          lds[swz<K>(gbase | (h * AH + 16 * mt + r))] = make_float2(re, im);
         }
       }
     }
@@ -599,7 +647,7 @@ unsigned grid_of(int64_t ntiles) { return unsigned(ntiles > (int64_t(1) << 22) ?
 
 template <int K, int M, int PREC, int OPS>
 hipError_t tile_mfma_k(const TilePlan &tp, float2 *psi, const void *op, hipStream_t st) {
-  constexpr int NT = 256;
+  constexpr int NT = 256 * KSplit<K, PREC, OPS>::value;
   constexpr int CHUNKS = (1 << (K + M)) / 2 / NT;
   TileArgs a;
   fill_args(tp, NT, CHUNKS, psi, op, &a);
