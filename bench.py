@@ -454,7 +454,10 @@ def main():
             "blocks_by_k": {str(k): v for k, v in sorted(kcount.items())}, "planner": "greedy",
             "parallelism": "single GPU",
         },
+        # algorithmic bytes of every sweep of the step over the whole step's time
+        # (reset and sampling included): the byte-weighted HBM efficiency of the sweeps
         "effective_gbps_per_step": sum(block_bytes) / (ms_per_step / 1e3) / 1e9,
+        "effective_frac_per_step": sum(block_bytes) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         # value counts every fused block that ran as one gate-sweep, also a diagonal block
         # whose cover visits part of the state; this rate counts full-state equivalents
         "full_sweep_equivalents_per_s": sum(block_bytes) / sweep_bytes / (ms_per_step / 1e3),
