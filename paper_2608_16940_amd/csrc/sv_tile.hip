@@ -564,8 +564,7 @@ __global__ __launch_bounds__((256 * KSplit<K, PREC, OPS>::value), (WavesPerSimd<
 __device__ __forceinline__ int lin_swz(int l, const int32_t *px) {
   int x = 0;
 #pragma unroll
-  for (int j = 0; j < 7; ++j)
-    if ((l >> (5 + j)) & 1) x ^= px[j];
+  for (int j = 0; j < 7; ++j) x ^= -((l >> (5 + j)) & 1) & px[j];  // no branches
   return l ^ x;
 }
 
@@ -586,11 +585,10 @@ __global__ __launch_bounds__(256) void k_tile_permute(TileArgs a) {
   int64_t goff_t = 0;
   int lamo_t = 0;
 #pragma unroll
-  for (int b = 1; b <= 8; ++b) {
-    if ((t >> (b - 1)) & 1) {
-      goff_t |= int64_t(1) << a.sbit[b];
-      lamo_t |= 1 << a.loc_out[b];
-    }
+  for (int b = 1; b <= 8; ++b) {  // without branches, as in k_tile_mfma
+    const int on = (t >> (b - 1)) & 1;
+    goff_t |= int64_t(on) << a.sbit[b];
+    lamo_t |= on << a.loc_out[b];
   }
   const int wr_t = lin_swz(2 * t, a.pswz);   // identity on load: local index 2t + 512 i
   const int rd_t = lin_swz(lamo_t, a.pswz);
